@@ -1,0 +1,95 @@
+"""Whole-transport pins of the oracle.
+
+* Per-event energy ledger closes exactly (sum of primary kinetic energies +
+  2m per annihilation - 2m per conversion = deposits + escaped + killed).
+* Results do not depend on the number of threads (per-track keyed streams,
+  Sec. 5.1).
+* Pencil photon beams into one slab (TestEm5-like layout, Sec. 4): the
+  fraction crossing without any interaction is exp(-mu x), binomial 3 sigma.
+* Shower sanity against the paper's TestEm3 numbers is reported, not gated
+  (different cuts and models).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gv_inputs
+
+ME = 0.51099895
+
+
+def _ledger_residual(prim, r):
+    Ein = np.bincount(prim["event"], weights=prim["ekin"])
+    L = r["ledger"]
+    lhs = Ein + 2 * ME * L[:, 3] - 2 * ME * L[:, 2]
+    rhs = r["edep"].sum(1) + L[:, 0] + L[:, 1]
+    return np.abs(lhs - rhs) / lhs
+
+
+@pytest.mark.parametrize("name,n", [("c1", 20), ("c2", 3), ("c3", 10), ("c4", 30), ("c5", 2)])
+def test_ledger_closure(oracle_mod, name, n):
+    geom, prim, seed = gv_inputs.workload(name, n)
+    o = oracle_mod.Oracle(geom)
+    r = o.transport(prim, seed)
+    assert _ledger_residual(prim, r).max() < 1e-10
+    c = r["counters"]
+    assert c["killed"] == 0 and c["rejection_exhausted"] == 0
+    # every conversion made exactly one positron, and each positron annihilated
+    # unless it escaped
+    assert c["proc_pair"] == c["tracks_positron"] - (prim["pdg"] == -11).sum()
+
+
+def test_thread_count_independence(oracle_mod):
+    geom, prim, seed = gv_inputs.workload("c3", 12)
+    o = oracle_mod.Oracle(geom)
+    a = o.transport(prim, seed, n_threads=1)
+    b = o.transport(prim, seed, n_threads=5)
+    assert np.array_equal(a["edep"], b["edep"])
+    assert np.array_equal(a["ledger"], b["ledger"])
+    assert a["counters"] == b["counters"]
+
+
+def test_seed_changes_history(oracle_mod):
+    geom, prim, seed = gv_inputs.workload("c1", 5)
+    o = oracle_mod.Oracle(geom)
+    a = o.transport(prim, seed)
+    b = o.transport(prim, seed + 1)
+    assert not np.array_equal(a["edep"], b["edep"])
+
+
+@pytest.mark.parametrize("mat,thick,k", [("Pb", 1.0, 0.2), ("Pb", 1.0, 10.0), ("lAr", 10.0, 1.0),
+                                         ("lAr", 10.0, 1e3)])
+def test_attenuation_exp_mu_x(oracle_mod, mat, thick, k):
+    geom = gv_inputs.single_slab(mat, thick)
+    o = oracle_mod.Oracle(geom)
+    n = 40_000
+    prim = gv_inputs.beam(n, 22, k, pos=(0.0, 0.0, -1.0))
+    r = o.transport(prim, 0xA77, trace_cap=40 * n)
+    tr = r["trace"]
+    assert r["counters"]["trace_dropped"] == 0
+    prim_steps = tr[tr["tid"] == 0]
+    interacted = np.zeros(n, dtype=bool)
+    interacted[prim_steps["event"][prim_steps["process"] >= 0]] = True
+    mu = o.table_value(0, "compton", k) + o.table_value(0, "pair", k)
+    # the tabulated mu agrees with the closed forms at this energy
+    mu_cf = o.lib.or_xs_compton(0, k) + o.lib.or_xs_pair(0, k)
+    assert abs(mu / mu_cf - 1) < 1e-3
+    p = math.exp(-mu * thick)
+    n_free = n - interacted.sum()
+    sigma = math.sqrt(n * p * (1 - p))
+    assert abs(n_free - n * p) < 3 * sigma + 1, (n_free, n * p, sigma)
+
+
+def test_testem3_shower_sanity(oracle_mod, capsys):
+    """Report only: 10 GeV e- in 50 Pb/lAr layers (no field here)."""
+    geom, prim, seed = gv_inputs.workload("c2", 4)
+    o = oracle_mod.Oracle(geom)
+    r = o.transport(prim, seed)
+    e = r["edep"]
+    pb, lar = e[:, 0::2].sum(1).mean(), e[:, 1::2].sum(1).mean()
+    with capsys.disabled():
+        print(f"\n[TestEm3-like, 4 events] Pb {pb/1e3:.3f} GeV, lAr {lar/1e3:.3f} GeV "
+              f"(paper, 0.7 mm cut + 4 T: 7.638 / 2.221 GeV)")
+    assert 8000 < pb + lar < 10000
+    assert 0.15 < lar / (pb + lar) < 0.3
