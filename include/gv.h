@@ -1,0 +1,269 @@
+/*
+ * gv.h -- C ABI of the MI355X (gfx950) basketised EM-shower stepping library.
+ *
+ * The library transports electrons, positrons and photons through a layered
+ * detector (a 1-D stack of slabs or cylindrical shells inside an envelope inside
+ * a vacuum world, optionally in a uniform magnetic field) and scores the energy
+ * each event deposits in each cell.  It is the data-parallel hot path of the
+ * GeantV method (arXiv 2005.00949): instead of following one track at a time,
+ * every stage of a step runs over whole track populations (Sec. 2, "algorithm-
+ * centric" stepping; stage order of Sec. 2.1.2), here as HIP kernels over
+ * structure-of-arrays track state resident in HBM.
+ *
+ * Conventions for every function:
+ *   * Return value: GV_OK (0) or one of the gv_status codes; gv_last_error()
+ *     then returns a human-readable message (thread-local, valid until the
+ *     next call from the same thread).
+ *   * Pointers are host pointers unless stated otherwise.  The library copies
+ *     what it needs before returning; the caller keeps ownership of every
+ *     buffer it passes.
+ *   * One context per process, bound to the HIP device that is current at
+ *     gv_init.  Calls are not re-entrant (GV_E_STATE if a transport is running).
+ *   * Units: cm, MeV, tesla.
+ */
+#ifndef GV_H
+#define GV_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GV_MAX_ELEM 8
+#define GV_MAX_MATS 16
+#define GV_MAX_VOLS 1024
+
+typedef enum {
+    GV_OK = 0,
+    GV_E_INVALID_ARG = 1,   /* null pointer, bad size, bad primary, bad config value */
+    GV_E_GEOMETRY = 2,      /* stack bounds not increasing, material/cell out of range */
+    GV_E_TABLES = 3,        /* table grid or cuts invalid, non-finite/non-positive table */
+    GV_E_HIP = 4,           /* a HIP runtime call failed (message holds the HIP error) */
+    GV_E_NOT_INIT = 5,      /* gv_init has not succeeded */
+    GV_E_CAPACITY = 6,      /* track queues overflow even with one event in flight */
+    GV_E_STATE = 7          /* call while a transport is running */
+} gv_status;
+
+enum { GV_AXIS_Z_SLABS = 0, GV_AXIS_R_SHELLS = 1 };
+enum { GV_DRIVER_PLAIN = 0, GV_DRIVER_BATCHED = 1 };
+enum { GV_P64 = 0, GV_PMIX = 1 };
+enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1 };
+
+/* A material: density and elemental composition by mass fraction.  The
+ * library derives electron density, radiation length (Tsai, unless X0_cm > 0),
+ * mean excitation energy (Bragg additivity of I_elem_eV, unless I_eV > 0) and
+ * plasma energy (density effect). */
+typedef struct {
+    double density;                 /* g/cm^3, > 0 */
+    int32_t n_elem;                 /* 1..GV_MAX_ELEM */
+    int32_t Z[GV_MAX_ELEM];
+    double A[GV_MAX_ELEM];          /* g/mol */
+    double w[GV_MAX_ELEM];          /* mass fractions, summing to 1 */
+    double I_elem_eV[GV_MAX_ELEM];
+    double I_eV;
+    double X0_cm;
+} gv_material;
+
+/* Layered geometry (GeomQuery, Sec. 3.4, for a 1-D stack).  Volume ids:
+ * 0 = vacuum world, 1..n_vol = stack volumes, -1 = outside the world.
+ *   GV_AXIS_Z_SLABS : volume v is |x| <= env[0], |y| <= env[1],
+ *                     z in [bounds[v-1], bounds[v]]; world box
+ *                     |x| <= world[0], |y| <= world[1], z in [world[2], world[3]].
+ *   GV_AXIS_R_SHELLS: volume v is r in [bounds[v-1], bounds[v]], |z| <= env[0]
+ *                     (bounds[0] may be 0); world cylinder r <= world[0],
+ *                     |z| <= world[1].
+ * material[v-1] indexes the materials array (-1 = vacuum); cell[v-1] is the
+ * scoring cell (-1 = none; every non-vacuum volume needs a cell). */
+typedef struct {
+    int32_t axis;
+    int32_t n_vol;                  /* 1..GV_MAX_VOLS */
+    const double* bounds;           /* n_vol + 1, strictly increasing */
+    const int32_t* material;        /* n_vol */
+    const int32_t* cell;            /* n_vol */
+    double env[2];
+    double world[4];
+    double B[3];                    /* uniform field, tesla */
+} gv_geometry;
+
+/* Table grid and thresholds from which gv_init builds, on the device, the
+ * per-material cross-section, restricted stopping-power and range tables
+ * (log grid e_min * 10^(i / bins_per_decade), i < n_nodes; linear
+ * interpolation in E; range by Gauss-Legendre quadrature of 1/S). */
+typedef struct {
+    double e_min_MeV;               /* first node, > 0 */
+    double bins_per_decade;         /* > 0 */
+    int32_t n_nodes;                /* 2..8192, last node >= highest primary energy */
+    int32_t reserved;
+    double t_cut_MeV;               /* delta-ray production threshold */
+    double k_cut_MeV;               /* bremsstrahlung photon threshold */
+    double t_track_MeV;             /* e+- tracking cut; gammas below are absorbed */
+} gv_tables;
+
+/* One primary track (64 bytes).  Events are 0..E-1 with E = 1 + max(event);
+ * a primary's order of appearance within its event is its track id. */
+typedef struct {
+    int32_t pdg;                    /* 11 (e-), -11 (e+), 22 (gamma) */
+    int32_t event;                  /* >= 0 */
+    double ekin_MeV;                /* (0, last table node] */
+    double pos_cm[3];
+    double dir[3];                  /* |dir| within 1e-6 of 1; renormalised */
+} gv_primary;
+
+/* Run options (defaults apply until gv_configure is called). */
+typedef struct {
+    int32_t driver;                 /* GV_DRIVER_PLAIN (one kernel per stage, host loop) or
+                                       GV_DRIVER_BATCHED (persistent kernel over per-type
+                                       queues, graph-captured step loop); default BATCHED */
+    int32_t precision;              /* GV_P64 or GV_PMIX; PLAIN supports GV_P64 only */
+    int32_t basket;                 /* tracks per claimed basket, 64..4096 (power of 2), 0 = tuned */
+    int32_t occupancy;              /* workgroups per CU of the persistent kernel, 0 = tuned */
+    int32_t inner_steps;            /* max steps a track takes in registers per launch, 0 = tuned */
+    int32_t graph_steps;            /* step launches per captured graph, 0 = default */
+    int32_t field_method;           /* GV_FIELD_HELIX or GV_FIELD_RK4 */
+    int32_t edep_on_device;         /* edep_out of gv_transport is a device pointer */
+    int64_t max_steps_per_track;    /* looper cap, default 2^20 (< 2^24) */
+    int64_t capacity;               /* track slots per particle-type queue, 0 = default */
+    int64_t max_events_in_flight;   /* 0 = all */
+    double chord_tol_cm;            /* field: allowed bending deviation, default 1e-3 */
+    double push_cm;                 /* field: push past a boundary, default 1e-7 */
+    double rk_frac;                 /* RK4 substep as a fraction of the radius, default 0.05 */
+    void* hip_stream;               /* hipStream_t to run on; NULL = the library's own */
+    int64_t trace_cap;              /* > 0: record up to this many step records (tests) */
+} gv_config;
+
+/* Counters of the last gv_transport. */
+typedef struct {
+    int64_t steps[3];               /* by type: gamma, e-, e+ (every propagation counts) */
+    int64_t tracks[3];              /* tracks created, by type (primaries included) */
+    int64_t interactions[8];        /* compton, pair, moller, bhabha, brems e-, brems e+,
+                                       annihilation at rest, null (empty sampling interval) */
+    int64_t escaped, killed, rejection_exhausted;
+    int64_t iterations;             /* step launches */
+    int64_t graph_replays;
+    int64_t trace_records;
+    int64_t overflow_restarts;
+    double e_in, e_dep, e_escaped, e_killed;   /* MeV, all events */
+    double n_pair, n_annih;
+    double transport_ms;            /* wall time of gv_transport */
+    double init_ms;                 /* wall time of gv_init (tables, uploads) */
+    double kernel_ms;               /* summed duration of the step kernels (HIP events) */
+    int64_t kernel_launches;        /* step-kernel launches timed into kernel_ms */
+    double alg_bytes;               /* algorithmic HBM bytes of track state moved */
+    int32_t driver, precision, basket, occupancy, inner_steps, graph_steps;
+    int64_t capacity;
+} gv_stats_t;
+
+/* Step-record layout written when trace_cap > 0 (112 bytes). */
+typedef struct {
+    uint64_t tid;
+    uint32_t event, nstep;
+    int32_t type, limiter, vol_pre, vol_post, process, n_children;
+    double pos[3], dir[3];
+    double ekin, edep, step;
+} gv_trace_rec;
+
+/* Set up materials, geometry and tables on the current HIP device; replaces
+ * any previous context.  Errors: GV_E_INVALID_ARG, GV_E_GEOMETRY,
+ * GV_E_TABLES, GV_E_HIP. */
+int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom,
+            const gv_tables* tables);
+
+/* Replace the run options (validated; GV_E_INVALID_ARG on bad values). */
+int gv_configure(const gv_config* cfg);
+
+/* Transport n primaries with run seed `seed` and score deposits.
+ * edep_out: E x n_cells doubles, row-major [event][cell], MeV; host memory
+ * unless edep_on_device.  Zero-filled, then accumulated; complete on return.
+ * Random numbers: Philox4x32-10 keyed by the seed, counter (event, track id,
+ * step, purpose) (the per-track streams of Sec. 5.1).  Errors:
+ * GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_CAPACITY, GV_E_HIP, GV_E_STATE. */
+int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* edep_out);
+
+/* Counters of the last transport. */
+int gv_stats(gv_stats_t* out);
+
+/* Per-event ledger of the last transport: n_events x 4 doubles
+ * (escaped energy, killed energy, conversions, annihilations). */
+int gv_ledger(double* out, int64_t n_events);
+
+/* Step records of the last transport (trace_cap > 0); *n_out = records copied. */
+int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out);
+
+/* Number of scoring cells of the current geometry. */
+int gv_n_cells(int32_t* out);
+
+/* Release device memory; the context must be re-initialised to be used. */
+void gv_finalize(void);
+
+const char* gv_last_error(void);
+
+/* ---------------- test entry points ---------------- */
+
+enum {
+    GV_DBG_STEP = 0,        /* one complete step of independent tracks */
+    GV_DBG_PHILOX = 1,      /* raw Philox4x32-10 blocks */
+    GV_DBG_COMPACT = 2,     /* stable three-way compaction (queue management) */
+    GV_DBG_TABLE = 3,       /* read back a built table (node values) */
+    GV_DBG_GEOM = 4         /* distance to boundary, next volume, safety, locate */
+};
+
+/* Host arrays for the test entry point; which fields are read or written
+ * depends on the stage:
+ *   GV_DBG_STEP   in : type, pos[3n], dir[3n], ekin, event, tid, nstep, precision, seed
+ *                 out: pos, dir, ekin, edep, vol, vol_pre, limiter, process, status,
+ *                      n_children, ch_type[2n], ch_ekin[2n], ch_dir[6n], ch_tid[2n],
+ *                      step, s_phys, d_bnd, safety
+ *   GV_DBG_PHILOX in : words[6n] = counter(4), key(2);  out: words_out[4n]
+ *   GV_DBG_COMPACT in: codes[3n] (output type 0..2 or -1 for the survivor and the
+ *                      two child slots of each input), block;  out: index[3 * 3n]
+ *                      (queue q at index + q*3n: input*4 + slot), counts[3]
+ *   GV_DBG_TABLE  in : material, which (table id), precision;  out: values[n]
+ *   GV_DBG_GEOM   in : pos, dir, vol (-2 = locate first);  out: d_bnd, vol (next),
+ *                      vol_pre (located volume), safety */
+typedef struct {
+    int32_t precision;
+    int32_t block;
+    int32_t material;
+    int32_t which;
+    uint64_t seed;
+    const int32_t* type;
+    const double* pos_in;
+    const double* dir_in;
+    const double* ekin_in;
+    const uint32_t* event;
+    const uint64_t* tid;
+    const uint32_t* nstep;
+    const int32_t* vol_in;
+    const uint32_t* words;
+    const int8_t* codes;
+    double* pos;
+    double* dir;
+    double* ekin;
+    double* edep;
+    int32_t* vol;
+    int32_t* vol_pre;
+    int32_t* limiter;
+    int32_t* process;
+    int32_t* status;
+    int32_t* n_children;
+    int32_t* ch_type;
+    double* ch_ekin;
+    double* ch_dir;
+    uint64_t* ch_tid;
+    double* step;
+    double* s_phys;
+    double* d_bnd;
+    double* safety;
+    uint32_t* words_out;
+    int32_t* index;
+    int64_t* counts;
+    double* values;
+} gv_debug_io;
+
+/* Run one test stage on n inputs (GV_DBG_TABLE: n = number of nodes). */
+int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -352,8 +352,12 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
         }
     } else {
         double p = sqrt(T_pre * (T_pre + 2.0 * OR_ME));
-        double upar = (t->dir[0] * G.B[0] + t->dir[1] * G.B[1] + t->dir[2] * G.B[2]) / Bm;
-        double sin2 = 1.0 - upar * upar;
+        /* transverse momentum relative to B: p |u x B/|B|| */
+        double b[3] = {G.B[0] / Bm, G.B[1] / Bm, G.B[2] / Bm};
+        double cx = t->dir[1] * b[2] - t->dir[2] * b[1];
+        double cy = t->dir[2] * b[0] - t->dir[0] * b[2];
+        double cz = t->dir[0] * b[1] - t->dir[1] * b[0];
+        double sin2 = cx * cx + cy * cy + cz * cz;
         double rcurv = INF_LEN, dfield = INF_LEN;
         if (sin2 > 0.0) {
             rcurv = p / (OR_KB * Bm * sqrt(sin2));

@@ -1,0 +1,47 @@
+"""Build libgv.so (HIP, gfx950) in-tree: paper_2005_00949_amd/_build/libgv.so."""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(OUT_DIR, "libgv.so")
+ARCH = "gfx950"
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found: the gfx950 library cannot be built")
+
+
+def flags(debug: bool = False):
+    f = ["-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-O3",
+         # no packed FP32 instructions anywhere in device code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         "-I", os.path.join(HERE, "..", "include")]
+    if debug:
+        f += ["-g"]
+    return f
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    src = os.path.join(CSRC, "gv_lib.hip")
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = [hipcc()] + flags() + (extra or []) + ["-o", tmp, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, cwd=OUT_DIR)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True, extra=sys.argv[1:]))

@@ -1,0 +1,342 @@
+// gv_geom.h -- layered-detector geometry on the device (GeomQuery stage of
+// Sec. 3.4 for a 1-D stack of volumes).
+//
+// Volume ids: 0 = vacuum world, 1..n = stack volumes, -1 = outside.  A slab
+// stack is a set of boxes sharing |x| <= env0, |y| <= env1 and tiling z; a
+// shell stack is a set of coaxial cylindrical shells tiling r within
+// |z| <= env0.  Adjacent stack volumes differ by one in their id, so the
+// navigator reduces to a ray-plane / ray-cylinder exit, the isotropic safety,
+// and "next = v +- 1 or the world".  The world entry into the envelope is the
+// overlap of the ray's parameter intervals (direction aware on surfaces).
+//
+// Every distance also names the plane face it ends on (axis, value) so that a
+// straight boundary-limited step places the point exactly on the plane.
+// Ties between faces resolve in the order x-, x+, y-, y+, z-, z+ (shells:
+// inner, outer, z-, z+) with strict comparisons.  All arithmetic is double:
+// positions and boundaries stay FP64 under every precision policy.
+#pragma once
+#include "gv_common.h"
+
+#ifndef GV_MAX_VOLS
+#define GV_MAX_VOLS 1024
+#endif
+
+namespace gv {
+
+struct DevGeom {
+    int axis;                     // 0 slabs along z, 1 shells along r
+    int n_vol;
+    int n_cells;
+    int n_mats;
+    double env[2];
+    double world[4];
+    double B[3];
+    double Bmag;
+    double bounds[GV_MAX_VOLS + 1];
+    int vmat[GV_MAX_VOLS];
+    int vcell[GV_MAX_VOLS];
+};
+
+struct Hit {
+    double t;
+    int next;
+    int snap_axis;                // -1: ends on a cylinder or leaves the world
+    double snap_val;
+};
+
+__device__ __forceinline__ int vol_material(const DevGeom& g, int v) { return v >= 1 ? g.vmat[v - 1] : -1; }
+__device__ __forceinline__ int vol_cell(const DevGeom& g, int v) { return v >= 1 ? g.vcell[v - 1] : -1; }
+
+// stack volume containing coordinate c along the stack axis: bounds[v-1] <= c < bounds[v]
+__device__ __forceinline__ int stack_of(const DevGeom& g, double c)
+{
+    if (c <= g.bounds[0]) return 1;
+    if (c >= g.bounds[g.n_vol]) return g.n_vol;
+    int lo = 0, hi = g.n_vol;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.bounds[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo + 1;
+}
+
+__device__ inline int locate(const DevGeom& g, const double p[3])
+{
+    if (g.axis == 0) {
+        if (fabs(p[0]) <= g.env[0] && fabs(p[1]) <= g.env[1] && p[2] >= g.bounds[0] && p[2] <= g.bounds[g.n_vol])
+            return stack_of(g, p[2]);
+        if (fabs(p[0]) <= g.world[0] && fabs(p[1]) <= g.world[1] && p[2] >= g.world[2] && p[2] <= g.world[3])
+            return 0;
+        return kOutside;
+    }
+    const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
+    if (r <= g.bounds[g.n_vol] && fabs(p[2]) <= g.env[0]) return stack_of(g, r);
+    if (r <= g.world[0] && fabs(p[2]) <= g.world[1]) return 0;
+    return kOutside;
+}
+
+// ---- slabs ----------------------------------------------------------------
+
+__device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], const double d[3])
+{
+    const double lo[3] = {-g.env[0], -g.env[1], g.bounds[v - 1]};
+    const double hi[3] = {g.env[0], g.env[1], g.bounds[v]};
+    double best = kInf;
+    int face = 5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] < 0.0) {
+            const double t = (lo[a] - p[a]) / d[a];
+            if (t < best) { best = t; face = 2 * a; }
+        } else if (d[a] > 0.0) {
+            const double t = (hi[a] - p[a]) / d[a];
+            if (t < best) { best = t; face = 2 * a + 1; }
+        }
+    }
+    Hit h;
+    h.t = best > 0.0 ? best : 0.0;
+    h.next = face == 4 ? (v == 1 ? 0 : v - 1) : face == 5 ? (v == g.n_vol ? 0 : v + 1) : 0;
+    h.snap_axis = face >> 1;
+    h.snap_val = (face & 1) ? hi[face >> 1] : lo[face >> 1];
+    return h;
+}
+
+__device__ inline double slab_safety(const DevGeom& g, int v, const double p[3])
+{
+    double s = fmin(p[2] - g.bounds[v - 1], g.bounds[v] - p[2]);
+    s = fmin(s, g.env[0] - fabs(p[0]));
+    s = fmin(s, g.env[1] - fabs(p[1]));
+    return s > 0.0 ? s : 0.0;
+}
+
+__device__ inline Hit slab_world(const DevGeom& g, const double p[3], const double d[3])
+{
+    const double lo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
+    const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
+    double tn = -kInf, tf = kInf;
+    int an = -1;
+    bool miss = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            miss = miss || p[a] < lo[a] || p[a] > hi[a];
+        } else {
+            const double t1 = (lo[a] - p[a]) / d[a], t2 = (hi[a] - p[a]) / d[a];
+            const double tmin = fmin(t1, t2), tmax = fmax(t1, t2);
+            if (tmin > tn) { tn = tmin; an = a; }
+            if (tmax < tf) tf = tmax;
+        }
+    }
+    Hit h;
+    h.t = kInf;
+    h.next = 0;
+    h.snap_axis = -1;
+    h.snap_val = 0.0;
+    if (!miss && tn <= tf && tf > 0.0) {
+        if (tn > 0.0) {
+            h.t = tn;
+            h.snap_axis = an;
+            h.snap_val = d[an] > 0.0 ? lo[an] : hi[an];
+            h.next = an == 2 ? (d[2] > 0.0 ? 1 : g.n_vol) : stack_of(g, p[2] + tn * d[2]);
+        } else {
+            h.t = 0.0;
+            h.next = stack_of(g, p[2]);
+        }
+    }
+    const double wlo[3] = {-g.world[0], -g.world[1], g.world[2]};
+    const double whi[3] = {g.world[0], g.world[1], g.world[3]};
+    double tw = kInf;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = kInf;
+        if (d[a] < 0.0) t = (wlo[a] - p[a]) / d[a];
+        else if (d[a] > 0.0) t = (whi[a] - p[a]) / d[a];
+        tw = t < tw ? t : tw;
+    }
+    tw = tw > 0.0 ? tw : 0.0;
+    if (!(h.t <= tw)) {
+        h.t = tw;
+        h.next = kOutside;
+        h.snap_axis = -1;
+        h.snap_val = 0.0;
+    }
+    return h;
+}
+
+__device__ inline double slab_world_safety(const DevGeom& g, const double p[3])
+{
+    double s = fmin(g.world[0] - fabs(p[0]), g.world[1] - fabs(p[1]));
+    s = fmin(s, fmin(p[2] - g.world[2], g.world[3] - p[2]));
+    const double zc = 0.5 * (g.bounds[0] + g.bounds[g.n_vol]);
+    const double zh = 0.5 * (g.bounds[g.n_vol] - g.bounds[0]);
+    const double qx = fmax(fabs(p[0]) - g.env[0], 0.0);
+    const double qy = fmax(fabs(p[1]) - g.env[1], 0.0);
+    const double qz = fmax(fabs(p[2] - zc) - zh, 0.0);
+    s = fmin(s, sqrt(qx * qx + qy * qy + qz * qz));
+    return s > 0.0 ? s : 0.0;
+}
+
+// ---- shells ---------------------------------------------------------------
+
+// leave the cylinder of radius R from inside (far root)
+__device__ __forceinline__ double cyl_out(const double p[3], const double d[3], double R)
+{
+    const double a = d[0] * d[0] + d[1] * d[1];
+    if (a == 0.0) return kInf;
+    const double b = p[0] * d[0] + p[1] * d[1];
+    const double c = p[0] * p[0] + p[1] * p[1] - R * R;
+    const double q = sqrt(fmax(b * b - a * c, 0.0));
+    return b <= 0.0 ? (q - b) / a : -c / (b + q);
+}
+
+// reach the cylinder of radius R from outside while moving inward (near root)
+__device__ __forceinline__ double cyl_in(const double p[3], const double d[3], double R)
+{
+    const double a = d[0] * d[0] + d[1] * d[1];
+    const double b = p[0] * d[0] + p[1] * d[1];
+    if (a == 0.0 || b >= 0.0) return kInf;
+    const double c = p[0] * p[0] + p[1] * p[1] - R * R;
+    const double disc = b * b - a * c;
+    if (disc < 0.0) return kInf;
+    return c / (sqrt(disc) - b);
+}
+
+__device__ inline Hit shell_exit(const DevGeom& g, int v, const double p[3], const double d[3])
+{
+    const double rin = g.bounds[v - 1], rout = g.bounds[v], H = g.env[0];
+    double best = kInf;
+    int face = -1;
+    if (rin > 0.0) {
+        const double t = cyl_in(p, d, rin);
+        if (t < best) { best = t; face = 0; }
+    }
+    {
+        const double t = cyl_out(p, d, rout);
+        if (t < best) { best = t; face = 1; }
+    }
+    if (d[2] < 0.0) {
+        const double t = (-H - p[2]) / d[2];
+        if (t < best) { best = t; face = 2; }
+    } else if (d[2] > 0.0) {
+        const double t = (H - p[2]) / d[2];
+        if (t < best) { best = t; face = 3; }
+    }
+    Hit h;
+    h.t = best > 0.0 ? best : 0.0;
+    h.snap_axis = -1;
+    h.snap_val = 0.0;
+    if (face == 0) h.next = v - 1;
+    else if (face == 1) h.next = v == g.n_vol ? 0 : v + 1;
+    else {
+        h.next = 0;
+        h.snap_axis = 2;
+        h.snap_val = face == 2 ? -H : H;
+    }
+    return h;
+}
+
+__device__ inline double shell_safety(const DevGeom& g, int v, const double p[3])
+{
+    const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
+    const double rin = g.bounds[v - 1];
+    double s = g.bounds[v] - r;
+    if (rin > 0.0) s = fmin(s, r - rin);
+    s = fmin(s, g.env[0] - fabs(p[2]));
+    return s > 0.0 ? s : 0.0;
+}
+
+__device__ inline Hit shell_world(const DevGeom& g, const double p[3], const double d[3])
+{
+    const double R = g.bounds[g.n_vol], H = g.env[0];
+    Hit h;
+    h.t = kInf;
+    h.next = 0;
+    h.snap_axis = -1;
+    h.snap_val = 0.0;
+    // parameter interval inside the infinite cylinder r <= R
+    const double a = d[0] * d[0] + d[1] * d[1];
+    const double b = p[0] * d[0] + p[1] * d[1];
+    const double c = p[0] * p[0] + p[1] * p[1] - R * R;
+    double c0 = -kInf, c1 = kInf;
+    bool miss = false;
+    if (a == 0.0) {
+        miss = c > 0.0;
+    } else {
+        const double disc = b * b - a * c;
+        if (disc < 0.0) {
+            miss = true;
+        } else {
+            const double sq = sqrt(disc);
+            const double q = b >= 0.0 ? -(b + sq) : sq - b;
+            const double r1 = q / a, r2 = q != 0.0 ? c / q : 0.0;
+            c0 = fmin(r1, r2);
+            c1 = fmax(r1, r2);
+        }
+    }
+    // parameter interval inside the slab |z| <= H
+    double z0 = -kInf, z1 = kInf;
+    if (d[2] == 0.0) {
+        miss = miss || fabs(p[2]) > H;
+    } else {
+        const double ta = (-H - p[2]) / d[2], tb = (H - p[2]) / d[2];
+        z0 = fmin(ta, tb);
+        z1 = fmax(ta, tb);
+    }
+    if (!miss) {
+        const double tn = fmax(c0, z0), tf = fmin(c1, z1);
+        if (tn <= tf && tf > 0.0) {
+            if (tn > 0.0) {
+                h.t = tn;
+                if (z0 > c0) {
+                    const double x = p[0] + tn * d[0], y = p[1] + tn * d[1];
+                    h.next = stack_of(g, sqrt(x * x + y * y));
+                    h.snap_axis = 2;
+                    h.snap_val = d[2] > 0.0 ? -H : H;
+                } else {
+                    h.next = g.n_vol;
+                }
+            } else {
+                h.t = 0.0;
+                h.next = stack_of(g, sqrt(p[0] * p[0] + p[1] * p[1]));
+            }
+        }
+    }
+    double tw = cyl_out(p, d, g.world[0]);
+    if (d[2] < 0.0) tw = fmin(tw, (-g.world[1] - p[2]) / d[2]);
+    else if (d[2] > 0.0) tw = fmin(tw, (g.world[1] - p[2]) / d[2]);
+    tw = tw > 0.0 ? tw : 0.0;
+    if (!(h.t <= tw)) {
+        h.t = tw;
+        h.next = kOutside;
+        h.snap_axis = -1;
+        h.snap_val = 0.0;
+    }
+    return h;
+}
+
+__device__ inline double shell_world_safety(const DevGeom& g, const double p[3])
+{
+    const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
+    const double R = g.bounds[g.n_vol], H = g.env[0];
+    const double dr = r - R, dz = fabs(p[2]) - H;
+    const double de = dz <= 0.0 ? dr : (dr <= 0.0 ? dz : sqrt(dr * dr + dz * dz));
+    const double s = fmin(fmin(g.world[0] - r, g.world[1] - fabs(p[2])), de);
+    return s > 0.0 ? s : 0.0;
+}
+
+// ---- dispatch -------------------------------------------------------------
+
+__device__ inline Hit distance_out(const DevGeom& g, int v, const double p[3], const double d[3])
+{
+    if (g.axis == 0) return v == 0 ? slab_world(g, p, d) : slab_exit(g, v, p, d);
+    return v == 0 ? shell_world(g, p, d) : shell_exit(g, v, p, d);
+}
+
+__device__ inline double safety(const DevGeom& g, int v, const double p[3])
+{
+    if (g.axis == 0) return v == 0 ? slab_world_safety(g, p) : slab_safety(g, v, p);
+    return v == 0 ? shell_world_safety(g, p) : shell_safety(g, v, p);
+}
+
+}  // namespace gv

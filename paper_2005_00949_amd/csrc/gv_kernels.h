@@ -1,0 +1,787 @@
+// gv_kernels.h -- HIP kernels of the stepping library (gfx950, wave64).
+#pragma once
+#include "gv_common.h"
+#include "gv_compact.h"
+#include "gv_geom.h"
+#include "gv_physics.h"
+#include "gv_step.h"
+#include "../../include/gv.h"
+
+namespace gv {
+
+__constant__ DevGeom c_geom;
+__constant__ DevPhys c_phys;
+
+// ---------------------------------------------------------------------------
+// Track state in HBM: structure of arrays, one set per particle-type queue
+// (batched) or one mixed pool with a type column (plain).
+// ---------------------------------------------------------------------------
+template <class P> struct Soa {
+    using R = typename P::R;
+    double* x;
+    double* y;
+    double* z;
+    R* ux;
+    R* uy;
+    R* uz;
+    R* T;
+    int* vol;
+    uint32_t* ev;
+    uint64_t* tid;
+    uint32_t* nstep;
+    int8_t* type;  // plain pool only
+};
+
+template <class P>
+__device__ __forceinline__ void load_track(const Soa<P>& q, size_t i, int type, Track<P>& t)
+{
+    t.x[0] = q.x[i];
+    t.x[1] = q.y[i];
+    t.x[2] = q.z[i];
+    t.u[0] = q.ux[i];
+    t.u[1] = q.uy[i];
+    t.u[2] = q.uz[i];
+    t.T = q.T[i];
+    t.vol = q.vol[i];
+    t.ev = q.ev[i];
+    t.tid = q.tid[i];
+    t.nstep = q.nstep[i];
+    t.type = type;
+}
+
+template <class P> __device__ __forceinline__ void store_track(const Soa<P>& q, size_t i, const Track<P>& t)
+{
+    q.x[i] = t.x[0];
+    q.y[i] = t.x[1];
+    q.z[i] = t.x[2];
+    q.ux[i] = t.u[0];
+    q.uy[i] = t.u[1];
+    q.uz[i] = t.u[2];
+    q.T[i] = t.T;
+    q.vol[i] = t.vol;
+    q.ev[i] = t.ev;
+    q.tid[i] = t.tid;
+    q.nstep[i] = t.nstep;
+    if (q.type) q.type[i] = (int8_t)t.type;
+}
+
+template <class P, class R = typename P::R>
+__device__ __forceinline__ void store_child(const Soa<P>& q, size_t i, const Track<P>& parent, const Child<R>& c)
+{
+    q.x[i] = parent.x[0];
+    q.y[i] = parent.x[1];
+    q.z[i] = parent.x[2];
+    q.ux[i] = c.u[0];
+    q.uy[i] = c.u[1];
+    q.uz[i] = c.u[2];
+    q.T[i] = c.T;
+    q.vol[i] = parent.vol;
+    q.ev[i] = parent.ev;
+    q.tid[i] = c.tid;
+    q.nstep[i] = 0;
+    if (q.type) q.type[i] = (int8_t)c.type;
+}
+
+// global counters (gv_stats)
+enum : int { kCSteps = 0, kCTracks = 3, kCProc = 6, kCEscaped = 14, kCKilled = 15, kCRej = 16, kCLoads = 17,
+             kCStores = 18, kNCount = 19 };
+
+struct Sinks {
+    double* edep;                 // [event][cell]
+    double* ledger;               // [event][4]: escaped, killed, n_pair, n_annih
+    unsigned long long* counters; // kNCount
+    gv_trace_rec* trace;
+    unsigned long long* trace_n;
+    long long trace_cap;
+};
+
+template <class P, class R = typename P::R>
+__device__ inline void trace_step(const Sinks& S, const Track<P>& before_key, int vol_pre, const Track<P>& after,
+                                  const StepOut<R>& o, uint32_t nstep_pre)
+{
+    const unsigned long long k = atomicAdd(S.trace_n, 1ull);
+    if ((long long)k >= S.trace_cap) return;
+    gv_trace_rec r;
+    r.tid = before_key.tid;
+    r.event = before_key.ev;
+    r.nstep = nstep_pre;
+    r.type = before_key.type;
+    r.limiter = o.lim;
+    r.vol_pre = vol_pre;
+    r.vol_post = after.vol;
+    r.process = o.proc;
+    r.n_children = o.nchild;
+    for (int a = 0; a < 3; ++a) {
+        r.pos[a] = after.x[a];
+        r.dir[a] = (double)after.u[a];
+    }
+    r.ekin = (double)after.T;
+    r.edep = o.edep;
+    r.step = o.s;
+    S.trace[k] = r;
+}
+
+// ledger and rare counters of one step (escape, kill, conversions, annihilation)
+template <class R>
+__device__ __forceinline__ void account_rare(const Sinks& S, uint32_t ev, const StepOut<R>& o, unsigned* lds_cnt)
+{
+    if (o.status == kEscaped) {
+        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 0], o.e_escaped);
+        atomicAdd(&lds_cnt[kCEscaped], 1u);
+    } else if (o.status == kKilled) {
+        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], o.e_killed);
+        atomicAdd(&lds_cnt[kCKilled], 1u);
+    }
+    if (o.n_pair) unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 2], 1.0);
+    if (o.n_annih) {
+        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 3], 1.0);
+        atomicAdd(&lds_cnt[kCProc + kAnnih], 1u);
+    }
+    if (o.proc >= 0) atomicAdd(&lds_cnt[kCProc + o.proc], 1u);
+    if (o.rej_exhausted) atomicAdd(&lds_cnt[kCRej], (unsigned)o.rej_exhausted);
+    for (int c = 0; c < o.nchild; ++c) atomicAdd(&lds_cnt[kCTracks + o.ch[c].type], 1u);
+}
+
+__device__ __forceinline__ void deposit(const Sinks& S, uint32_t ev, int vol, double e)
+{
+    if (e == 0.0) return;
+    const int cell = vol_cell(c_geom, vol);
+    if (cell >= 0) unsafeAtomicAdd(&S.edep[(size_t)ev * c_geom.n_cells + cell], e);
+    else unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], e);
+}
+
+// ===========================================================================
+// Table builder (FP64 on the device)
+// ===========================================================================
+
+// node energies and per-node cross sections / stopping powers
+__global__ void k_build_xs(double* rec64, double* E64, float* E32)
+{
+    const int n = c_phys.n_nodes;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * c_phys.n_mats) return;
+    const int m = idx / n, i = idx - m * n;
+    const double E = c_phys.e_min * pow(10.0, (double)i / c_phys.bpd);
+    if (m == 0) {
+        E64[i] = E;
+        E32[i] = (float)E;
+    }
+    const DevMat& M = c_phys.mat[m];
+    double* g = rec64 + ((size_t)(m * 3 + kGamma) * n + i) * kCols;
+    double* e = rec64 + ((size_t)(m * 3 + kElectron) * n + i) * kCols;
+    double* p = rec64 + ((size_t)(m * 3 + kPositron) * n + i) * kCols;
+    g[0] = M.n_el * xs_kn_per_electron(E);
+    g[1] = xs_pair(M, E);
+    g[2] = 0.0;
+    g[3] = 0.0;
+    e[0] = xs_moller(M, E, c_phys.t_cut);
+    e[1] = xs_brems(M, E, c_phys.k_cut);
+    e[2] = dedx_total(M, E, false, c_phys.t_cut, c_phys.k_cut);
+    p[0] = xs_bhabha(M, E, c_phys.t_cut);
+    p[1] = xs_brems(M, E, c_phys.k_cut);
+    p[2] = dedx_total(M, E, true, c_phys.t_cut, c_phys.k_cut);
+}
+
+// 8-point Gauss-Legendre on [-1, 1]
+__device__ __constant__ double c_glx[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                                           -0.1834346424956498, 0.1834346424956498, 0.5255324099163290,
+                                           0.7966664774136267, 0.9602898564975363};
+__device__ __constant__ double c_glw[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                                           0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                                           0.2223810344533745, 0.1012285362903763};
+
+// range increment of each bin: int E/S(E) dlnE over [ln E_i, ln E_i+1]
+__global__ void k_build_range_bins(const double* E64, double* dR)
+{
+    const int n = c_phys.n_nodes;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = 2 * (n - 1);
+    if (idx >= per * c_phys.n_mats) return;
+    const int m = idx / per, r = idx - m * per;
+    const int pos = r / (n - 1), i = r - pos * (n - 1);
+    const double la = log(E64[i]), lb = log(E64[i + 1]);
+    const double h = 0.5 * (lb - la), c = 0.5 * (lb + la);
+    double s = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const double E = exp(c + h * c_glx[j]);
+        s += c_glw[j] * E / dedx_total(c_phys.mat[m], E, pos != 0, c_phys.t_cut, c_phys.k_cut);
+    }
+    dR[idx] = s * h;
+}
+
+// running sum from R(E_0) = E_0 / S(E_0), in node order
+__global__ void k_build_range_scan(double* rec64, const double* E64, const double* dR)
+{
+    const int n = c_phys.n_nodes;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * c_phys.n_mats) return;
+    const int m = idx / 2, pos = idx & 1;
+    double* base = rec64 + (size_t)(m * 3 + (pos ? kPositron : kElectron)) * n * kCols;
+    const double* d = dR + (size_t)(m * 2 + pos) * (n - 1);
+    double R = E64[0] / dedx_total(c_phys.mat[m], E64[0], pos != 0, c_phys.t_cut, c_phys.k_cut);
+    base[3] = R;
+    for (int i = 0; i + 1 < n; ++i) {
+        R = R + d[i];
+        base[(i + 1) * kCols + 3] = R;
+    }
+}
+
+__global__ void k_to_float(const double* a, float* b, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// range at the tracking cut (per material, e-/e+), in both precisions
+__global__ void k_range_at_cut(const double* rec64, const double* E64, const float* rec32, const float* E32,
+                               double* out64, float* out32)
+{
+    const int idx = threadIdx.x;
+    if (idx >= 2 * c_phys.n_mats) return;
+    const int m = idx / 2, pos = idx & 1;
+    const int type = pos ? kPositron : kElectron;
+    TabView<double> t64{rec64, E64, c_phys.n_nodes};
+    TabView<float> t32{rec32, E32, c_phys.n_nodes};
+    {
+        const double T = c_phys.t_track;
+        const int i = find_bin(t64, T, c_phys.log10_emin, c_phys.bpd);
+        const double w = (T - E64[i]) / (E64[i + 1] - E64[i]);
+        out64[idx] = lerp_col(t64, tab_base(t64, m, type), i, 3, w);
+    }
+    {
+        const float T = (float)c_phys.t_track;
+        const int i = find_bin(t32, T, c_phys.log10_emin, c_phys.bpd);
+        const float w = (T - E32[i]) / (E32[i + 1] - E32[i]);
+        out32[idx] = lerp_col(t32, tab_base(t32, m, type), i, 3, w);
+    }
+}
+
+// ===========================================================================
+// Test kernels
+// ===========================================================================
+
+__global__ void k_dbg_philox(const uint32_t* in, uint32_t* out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* w = in + 6 * i;
+    const U4 r = philox(w[0], w[1], w[2], w[3], w[4], w[5]);
+    for (int a = 0; a < 4; ++a) out[4 * i + a] = r.w[a];
+}
+
+__global__ void k_dbg_geom(const double* pos, const double* dir, const int* vol_in, double* dbnd, int* next,
+                           int* vol_loc, double* saf, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    const double d[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+    const int v = vol_in[i] == -2 ? locate(c_geom, p) : vol_in[i];
+    vol_loc[i] = v;
+    if (v == kOutside) {
+        dbnd[i] = 0.0;
+        next[i] = kOutside;
+        saf[i] = 0.0;
+        return;
+    }
+    const Hit h = distance_out(c_geom, v, p, d);
+    dbnd[i] = h.t;
+    next[i] = h.next;
+    saf[i] = safety(c_geom, v, p);
+}
+
+struct DbgStepIO {
+    const int* type;
+    const double* pos_in;
+    const double* dir_in;
+    const double* ekin_in;
+    const uint32_t* event;
+    const uint64_t* tid;
+    const uint32_t* nstep;
+    double* pos;
+    double* dir;
+    double* ekin;
+    double* edep;
+    int* vol;
+    int* vol_pre;
+    int* lim;
+    int* proc;
+    int* status;
+    int* nchild;
+    int* ch_type;
+    double* ch_ekin;
+    double* ch_dir;
+    uint64_t* ch_tid;
+    double* step;
+    double* s_phys;
+    double* d_bnd;
+    double* safety;
+};
+
+template <class P>
+__global__ void k_dbg_step(DbgStepIO io, long long n, uint64_t seed, TabView<typename P::R> tv)
+{
+    using R = typename P::R;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Ctx<P> c{seed, &c_geom, &c_phys, tv};
+    Track<P> t;
+    for (int a = 0; a < 3; ++a) {
+        t.x[a] = io.pos_in[3 * i + a];
+        t.u[a] = (R)io.dir_in[3 * i + a];
+    }
+    t.T = (R)io.ekin_in[i];
+    t.type = io.type[i];
+    t.ev = io.event[i];
+    t.tid = io.tid[i];
+    t.nstep = io.nstep[i];
+    t.vol = locate(c_geom, t.x);
+    StepOut<R> o;
+    step_track(c, t, o);
+    for (int a = 0; a < 3; ++a) {
+        io.pos[3 * i + a] = t.x[a];
+        io.dir[3 * i + a] = (double)t.u[a];
+    }
+    io.ekin[i] = (double)t.T;
+    io.edep[i] = o.edep;
+    io.vol[i] = t.vol;
+    io.vol_pre[i] = o.vol_pre;
+    io.lim[i] = o.lim;
+    io.proc[i] = o.proc;
+    io.status[i] = o.status;
+    io.nchild[i] = o.nchild;
+    for (int k = 0; k < 2; ++k) {
+        const long long j = 2 * i + k;
+        if (k < o.nchild) {
+            io.ch_type[j] = o.ch[k].type;
+            io.ch_ekin[j] = (double)o.ch[k].T;
+            io.ch_tid[j] = o.ch[k].tid;
+            for (int a = 0; a < 3; ++a) io.ch_dir[3 * j + a] = (double)o.ch[k].u[a];
+        } else {
+            io.ch_type[j] = -1;
+            io.ch_ekin[j] = 0.0;
+            io.ch_tid[j] = 0;
+            for (int a = 0; a < 3; ++a) io.ch_dir[3 * j + a] = 0.0;
+        }
+    }
+    io.step[i] = o.s;
+    io.s_phys[i] = o.s_phys;
+    io.d_bnd[i] = o.d_bnd;
+    io.safety[i] = o.safety;
+}
+
+// stable three-way compaction of given output codes (same machinery as the
+// batched step kernel): queue q receives input*4 + slot in expanded order
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_dbg_compact(const int8_t* codes, long long n, int* outq, long long stride,
+                                                       uint32_t* counts, uint32_t* ticket, uint64_t* status,
+                                                       uint32_t epoch)
+{
+    __shared__ ScanShared<BLOCK> sh;
+    const long long n_chunks = (n + BLOCK - 1) / BLOCK;
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = (int)atomicAdd(ticket, 1u);
+        __syncthreads();
+        const long long chunk = sh.ticket;
+        __syncthreads();
+        if (chunk >= n_chunks) break;
+        const long long i = chunk * BLOCK + threadIdx.x;
+        int code[3] = {-1, -1, -1};
+        if (i < n)
+            for (int j = 0; j < 3; ++j) code[j] = codes[3 * i + j];
+        int cnt[3] = {0, 0, 0};
+        for (int j = 0; j < 3; ++j)
+            if (code[j] >= 0) cnt[code[j]]++;
+        int excl[3], tot[3];
+        block_scan3<BLOCK>(cnt, excl, tot, sh);
+        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh);
+        int local[3] = {0, 0, 0};
+        for (int j = 0; j < 3; ++j) {
+            const int q = code[j];
+            if (q < 0) continue;
+            const long long pos = (long long)sh.prefix[q] + excl[q] + local[q]++;
+            outq[q * stride + pos] = (int)(i * 4 + j);
+        }
+        if (chunk == n_chunks - 1 && threadIdx.x < 3) counts[threadIdx.x] = sh.prefix[threadIdx.x] + sh.total[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// Batched driver: persistent kernel over per-type queues
+// ===========================================================================
+
+struct Ctrl {
+    uint32_t count[2][4];   // queue sizes by buffer parity and type
+    uint32_t ticket;        // next basket to claim
+    uint32_t epoch;         // launch counter tagging look-back status words
+    uint32_t overflow;      // a queue ran out of capacity
+    uint32_t done;          // workgroups finished in this launch
+    uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
+};
+
+template <class P> struct BatchArgs {
+    Soa<P> q[2][3];          // [parity][type]
+    Ctrl* ctrl;
+    uint64_t* status;
+    uint32_t cap;
+    int parity;              // input buffer parity of this launch
+    int basket_chunks;       // chunks per claimed basket
+    int inner_bulk;          // steps per track per launch while the population is large
+    int inner_tail;          // ... and in the tail
+    uint32_t tail_threshold; // population below which the tail setting applies
+    Sinks S;
+    TabView<typename P::R> tv;
+};
+
+// Primary ingest (the event server of Sec. 2.1): validated, typed primaries
+// with their track id (order within the event) are located in the geometry,
+// renormalised and written into the queue slots the host assigned.
+struct PrimDev {
+    double x, y, z, ux, uy, uz, T;
+    int vol, type;
+    uint32_t ev;
+    uint64_t tid;
+};
+
+template <class P>
+__global__ void k_ingest(const PrimDev* prim, long long n, const uint32_t* slot, Soa<P> q0, Soa<P> q1, Soa<P> q2)
+{
+    using R = typename P::R;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PrimDev p = prim[i];
+    const Soa<P>& q = p.type == kGamma ? q0 : (p.type == kElectron ? q1 : q2);
+    const size_t k = slot[i];
+    const double pos[3] = {p.x, p.y, p.z};
+    const double nn = sqrt(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz);
+    q.x[k] = p.x;
+    q.y[k] = p.y;
+    q.z[k] = p.z;
+    q.ux[k] = (R)(p.ux / nn);
+    q.uy[k] = (R)(p.uy / nn);
+    q.uz[k] = (R)(p.uz / nn);
+    q.T[k] = (R)p.T;
+    q.vol[k] = locate(c_geom, pos);
+    q.ev[k] = p.ev;
+    q.tid[k] = p.tid;
+    q.nstep[k] = 0;
+    if (q.type) q.type[k] = (int8_t)p.type;
+}
+
+// end of a launch, run by the last workgroup to finish: the consumed input
+// counts become the next launch's (empty) output, the basket ticket restarts
+// and the look-back epoch advances.  Every workgroup has read the control
+// block before it increments `done`, so nothing reads these words afterwards.
+__device__ __forceinline__ void finish_launch(Ctrl* ctrl, int parity)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t d = atomicAdd(&ctrl->done, 1u);
+        if (d == gridDim.x - 1) {
+            __threadfence();
+            ctrl->count[parity][0] = 0;
+            ctrl->count[parity][1] = 0;
+            ctrl->count[parity][2] = 0;
+            ctrl->ticket = 0;
+            ctrl->done = 0;
+            ctrl->epoch = ctrl->epoch + 1;
+            __threadfence();
+        }
+    }
+}
+
+template <class P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
+{
+    using R = typename P::R;
+    __shared__ ScanShared<BLOCK> sh;
+    __shared__ unsigned cnt_lds[kNCount];
+    for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
+
+    const int pin = A.parity, pout = A.parity ^ 1;
+    const uint32_t n0 = A.ctrl->count[pin][0], n1 = A.ctrl->count[pin][1], n2 = A.ctrl->count[pin][2];
+    const uint32_t epoch = A.ctrl->epoch;
+    const uint32_t c0 = (n0 + BLOCK - 1) / BLOCK, c1 = (n1 + BLOCK - 1) / BLOCK, c2 = (n2 + BLOCK - 1) / BLOCK;
+    const uint32_t n_chunks = c0 + c1 + c2;
+    const uint32_t population = n0 + n1 + n2;
+    const int inner = population < A.tail_threshold ? A.inner_tail : A.inner_bulk;
+    Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
+    uint32_t steps_here[3] = {0, 0, 0};
+    uint32_t loads_here = 0, stores_here = 0;
+    __syncthreads();
+
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = (int)atomicAdd(&A.ctrl->ticket, 1u);
+        __syncthreads();
+        const uint32_t first = (uint32_t)sh.ticket * (uint32_t)A.basket_chunks;
+        __syncthreads();
+        if (first >= n_chunks) break;
+        const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
+        for (uint32_t chunk = first; chunk < last; ++chunk) {
+            int type;
+            uint32_t base, n_t;
+            if (chunk < c0) { type = kGamma; base = chunk * BLOCK; n_t = n0; }
+            else if (chunk < c0 + c1) { type = kElectron; base = (chunk - c0) * BLOCK; n_t = n1; }
+            else { type = kPositron; base = (chunk - c0 - c1) * BLOCK; n_t = n2; }
+            const uint32_t slot = base + threadIdx.x;
+            const bool active = slot < n_t;
+            Track<P> t;
+            StepOut<R> o;
+            o.status = kDead;
+            o.nchild = 0;
+            if (active) {
+                load_track(A.q[pin][type], slot, type, t);
+                loads_here += 1;
+                double acc = 0.0;
+                int acc_vol = t.vol;
+                for (int k = 0; k < inner; ++k) {
+                    const uint32_t ns = t.nstep;
+                    step_track(c, t, o);
+                    if (o.did_step) steps_here[type] += 1;
+                    if (o.vol_pre != acc_vol) {
+                        deposit(A.S, t.ev, acc_vol, acc);
+                        acc = 0.0;
+                        acc_vol = o.vol_pre;
+                    }
+                    acc += o.edep;
+                    if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
+                    account_rare(A.S, t.ev, o, cnt_lds);
+                    if (o.status != kAlive || o.nchild > 0) break;
+                }
+                deposit(A.S, t.ev, acc_vol, acc);
+            }
+            // outputs: survivor then children, each to the queue of its type
+            int code[3] = {-1, -1, -1};
+            if (active) {
+                if (o.status == kAlive) code[0] = type;
+                for (int k = 0; k < o.nchild; ++k) code[1 + k] = o.ch[k].type;
+            }
+            int cnt[3] = {0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (code[j] >= 0) cnt[code[j]]++;
+            int excl[3], tot[3];
+            block_scan3<BLOCK>(cnt, excl, tot, sh);
+            lookback3<BLOCK>(A.status, chunk, epoch, tot, sh);
+            int local[3] = {0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int q = code[j];
+                if (q < 0) continue;
+                const uint32_t pos = (uint32_t)sh.prefix[q] + (uint32_t)excl[q] + (uint32_t)local[q]++;
+                if (pos >= A.cap) {
+                    A.ctrl->overflow = 1u;
+                    continue;
+                }
+                if (j == 0) store_track(A.q[pout][q], pos, t);
+                else store_child(A.q[pout][q], pos, t, o.ch[j - 1]);
+                stores_here += 1;
+            }
+            if (chunk == n_chunks - 1 && threadIdx.x < 3) {
+                const uint32_t total = (uint32_t)(sh.prefix[threadIdx.x] + sh.total[threadIdx.x]);
+                A.ctrl->count[pout][threadIdx.x] = total < A.cap ? total : A.cap;
+            }
+            __syncthreads();
+        }
+    }
+    // flush counters
+    for (int ty = 0; ty < 3; ++ty) atomicAdd(&cnt_lds[kCSteps + ty], steps_here[ty]);
+    atomicAdd(&cnt_lds[kCLoads], loads_here);
+    atomicAdd(&cnt_lds[kCStores], stores_here);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNCount; i += BLOCK)
+        if (cnt_lds[i]) atomicAdd(&A.S.counters[i], (unsigned long long)cnt_lds[i]);
+    finish_launch(A.ctrl, pin);
+}
+
+// ===========================================================================
+// Plain FP64 driver: one kernel per stage, intermediates in HBM
+// ===========================================================================
+
+struct PlainArgs {
+    Soa<P64> pool;
+    Limits<double>* L;
+    Geo* G;
+    Prop<double>* pr;
+    StepOut<double>* o;
+    uint8_t* active;
+    uint8_t* stopped;
+    uint32_t* nsteps_pre;
+    int* vol_pre;
+    long long n;
+    uint64_t seed;
+    Sinks S;
+    TabView<double> tv;
+};
+
+__device__ __forceinline__ void plain_load(const PlainArgs& A, long long i, Track<P64>& t)
+{
+    load_track(A.pool, (size_t)i, (int)A.pool.type[i], t);
+}
+
+__global__ void k_plain_prestep_limit(PlainArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+    Track<P64> t;
+    plain_load(A, i, t);
+    StepOut<double> o;
+    init_out(t, o);
+    A.nsteps_pre[i] = t.nstep;
+    A.vol_pre[i] = t.vol;
+    const bool go = stage_prestep(c, t, o);
+    A.active[i] = go ? 1 : 0;
+    if (go) {
+        Limits<double> L;
+        stage_limit(c, t, L);
+        A.L[i] = L;
+    } else {
+        store_track(A.pool, (size_t)i, t);
+    }
+    A.o[i] = o;
+}
+
+__global__ void k_plain_geom(PlainArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || !A.active[i]) return;
+    Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+    Track<P64> t;
+    plain_load(A, i, t);
+    Geo G;
+    stage_geom(c, t, G);
+    A.G[i] = G;
+}
+
+__global__ void k_plain_move(PlainArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || !A.active[i]) return;
+    Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+    Track<P64> t;
+    plain_load(A, i, t);
+    const Limits<double> L = A.L[i];
+    const Geo G = A.G[i];
+    Prop<double> pr;
+    stage_move(c, t, L, G, pr);
+    A.pr[i] = pr;
+    store_track(A.pool, (size_t)i, t);
+    StepOut<double>& o = A.o[i];
+    o.did_step = 1;
+    o.s = pr.s;
+    o.lim = pr.lim;
+    o.s_phys = L.s_phys >= big_len<double>() ? kInf : L.s_phys;
+    o.d_bnd = G.d_bnd;
+    o.safety = G.safety;
+}
+
+__global__ void k_plain_msc(PlainArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || !A.active[i]) return;
+    Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+    Track<P64> t;
+    plain_load(A, i, t);
+    t.nstep = A.nsteps_pre[i];
+    stage_msc(c, t, A.L[i], A.pr[i]);
+    store_track(A.pool, (size_t)i, t);
+}
+
+__global__ void k_plain_eloss(PlainArgs A)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || !A.active[i]) return;
+    Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+    Track<P64> t;
+    plain_load(A, i, t);
+    StepOut<double> o = A.o[i];
+    A.stopped[i] = stage_eloss(c, t, A.L[i], A.pr[i], o) ? 1 : 0;
+    A.o[i] = o;
+    store_track(A.pool, (size_t)i, t);
+}
+
+__global__ void k_plain_finish(PlainArgs A)
+{
+    __shared__ unsigned cnt_lds[kNCount];
+    for (int k = threadIdx.x; k < kNCount; k += blockDim.x) cnt_lds[k] = 0;
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < A.n) {
+        Ctx<P64> c{A.seed, &c_geom, &c_phys, A.tv};
+        Track<P64> t;
+        plain_load(A, i, t);
+        StepOut<double> o = A.o[i];
+        if (A.active[i]) {
+            stage_finish(c, t, A.L[i], A.pr[i], A.stopped[i] != 0, o);
+            store_track(A.pool, (size_t)i, t);
+            atomicAdd(&cnt_lds[kCSteps + t.type], 1u);
+            if (A.S.trace) {
+                Track<P64> key = t;
+                trace_step(A.S, key, A.vol_pre[i], t, o, A.nsteps_pre[i]);
+            }
+        }
+        deposit(A.S, t.ev, A.vol_pre[i], o.edep);
+        account_rare(A.S, t.ev, o, cnt_lds);
+        A.o[i] = o;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kNCount; k += blockDim.x)
+        if (cnt_lds[k]) atomicAdd(&A.S.counters[k], (unsigned long long)cnt_lds[k]);
+}
+
+// survivors and children into the next pool, stable (single queue)
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_plain_compact(PlainArgs A, Soa<P64> next, Ctrl* ctrl, int parity,
+                                                         uint64_t* status, uint32_t cap)
+{
+    __shared__ ScanShared<BLOCK> sh;
+    const long long n_chunks = (A.n + BLOCK - 1) / BLOCK;
+    const uint32_t epoch = ctrl->epoch;
+    uint32_t* count_out = &ctrl->count[parity ^ 1][0];
+    uint32_t* overflow = &ctrl->overflow;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = (int)atomicAdd(&ctrl->ticket, 1u);
+        __syncthreads();
+        const long long chunk = sh.ticket;
+        __syncthreads();
+        if (chunk >= n_chunks) break;
+        const long long i = chunk * BLOCK + threadIdx.x;
+        int cnt[3] = {0, 0, 0};
+        Track<P64> t;
+        StepOut<double> o;
+        o.status = kDead;
+        o.nchild = 0;
+        if (i < A.n) {
+            plain_load(A, i, t);
+            o = A.o[i];
+            cnt[0] = (o.status == kAlive ? 1 : 0) + o.nchild;
+        }
+        int excl[3], tot[3];
+        block_scan3<BLOCK>(cnt, excl, tot, sh);
+        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh);
+        uint32_t pos = (uint32_t)sh.prefix[0] + (uint32_t)excl[0];
+        if (i < A.n) {
+            if (o.status == kAlive) {
+                if (pos < cap) store_track(next, pos, t);
+                else *overflow = 1u;
+                ++pos;
+            }
+            for (int k = 0; k < o.nchild; ++k, ++pos) {
+                if (pos < cap) store_child(next, pos, t, o.ch[k]);
+                else *overflow = 1u;
+            }
+        }
+        if (chunk == n_chunks - 1 && threadIdx.x == 0) {
+            const uint32_t total = (uint32_t)(sh.prefix[0] + sh.total[0]);
+            *count_out = total < cap ? total : cap;
+        }
+        __syncthreads();
+    }
+    finish_launch(ctrl, parity);
+}
+
+}  // namespace gv

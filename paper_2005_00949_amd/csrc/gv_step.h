@@ -1,0 +1,464 @@
+// gv_step.h -- one transport step of one track, split into the simulation
+// stages of Sec. 2.1.2:
+//   PreStep         (stage_prestep)   tracking cut / e+ annihilation at rest,
+//                                     looper cap, leaving the world
+//   ComputeIntLen   (stage_limit)     table cross sections, physics length from
+//                                     an exponential draw, continuous-loss limit
+//   GeomQuery       (stage_geom)      distance to boundary, next volume, safety
+//   Propagation     (stage_move)      straight line, or in a field the rule of
+//                                     Sec. 3.4: min(min(phys, boundary),
+//                                     max(field, safety)), helix/RK4, relocate
+//   PostPropagation (stage_msc)       Highland multiple scattering
+//   AlongStepAction (stage_eloss)     restricted continuous loss, deposit
+//   PostStepActions + SteppingActions (stage_finish)  discrete interaction at
+//                                     the post-loss energy, stop, escape
+// The plain driver runs each stage as its own kernel with the intermediates in
+// HBM; the batched driver runs the whole chain in registers (step_track).
+#pragma once
+#include "gv_common.h"
+#include "gv_geom.h"
+#include "gv_physics.h"
+
+namespace gv {
+
+template <class P> struct Track {
+    using R = typename P::R;
+    double x[3];
+    R u[3];
+    R T;
+    int vol;
+    int type;
+    uint32_t ev;
+    uint32_t nstep;
+    uint64_t tid;
+};
+
+template <class R> struct Child {
+    int type;
+    R T;
+    R u[3];
+    uint64_t tid;
+};
+
+// per-step outputs that leave the track itself
+template <class R> struct StepOut {
+    int status;         // kAlive / kDead / kEscaped / kKilled
+    int did_step;       // a propagation happened (counts as a step)
+    int lim;
+    int proc;           // -1 none
+    int vol_pre;        // volume whose cell receives edep
+    int nchild;
+    int rej_exhausted;
+    int n_pair, n_annih;
+    double edep;        // MeV, into cell(vol_pre)
+    double e_escaped, e_killed;
+    double s, s_phys, d_bnd, safety;
+    Child<R> ch[2];
+};
+
+template <class R> struct Limits {
+    R s_phys;   // physics length (kInf-like if no process)
+    R s_eloss;
+    R range;
+    R stot, sa;
+    R usel;
+    int m;      // material of the pre-step volume (-1 vacuum)
+};
+
+struct Geo {
+    double d_bnd;
+    double safety;
+    int next;
+    int snap_axis;
+    double snap_val;
+};
+
+template <class R> struct Prop {
+    double s;
+    R T_pre;
+    int lim;
+    int crossed;
+};
+
+template <class P> struct Ctx {
+    using R = typename P::R;
+    uint64_t seed;
+    const DevGeom* g;
+    const DevPhys* ph;
+    TabView<R> tv;
+};
+
+template <class R> __device__ __forceinline__ R big_len() { return (R)1.0e30; }
+
+template <class P, class R = typename P::R>
+__device__ __forceinline__ void init_out(const Track<P>& t, StepOut<R>& o)
+{
+    o.status = kAlive;
+    o.did_step = 0;
+    o.lim = -1;
+    o.proc = -1;
+    o.vol_pre = t.vol;
+    o.nchild = 0;
+    o.rej_exhausted = 0;
+    o.n_pair = 0;
+    o.n_annih = 0;
+    o.edep = 0.0;
+    o.e_escaped = 0.0;
+    o.e_killed = 0.0;
+    o.s = 0.0;
+    o.s_phys = 0.0;
+    o.d_bnd = 0.0;
+    o.safety = 0.0;
+}
+
+template <class P, class R = typename P::R>
+__device__ __forceinline__ void child_ids(const Ctx<P>& c, const Track<P>& t, uint64_t ids[2])
+{
+    const U4 b = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpChild);
+    ids[0] = ((uint64_t)b.w[1] << 32) | b.w[0];
+    ids[1] = ((uint64_t)b.w[3] << 32) | b.w[2];
+}
+
+template <class R> __device__ __forceinline__ void add_child(StepOut<R>& o, int type, R T, const R u[3], uint64_t tid)
+{
+    Child<R>& ch = o.ch[o.nchild++];
+    ch.type = type;
+    ch.T = T;
+    ch.u[0] = u[0];
+    ch.u[1] = u[1];
+    ch.u[2] = u[2];
+    ch.tid = tid;
+}
+
+// e+ at rest: two back-to-back 511 keV photons, isotropic (ANNIH block)
+template <class P, class R = typename P::R>
+__device__ inline void annihilate(const Ctx<P>& c, const Track<P>& t, StepOut<R>& o)
+{
+    const U4 b = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpAnnih);
+    const R ct = (R)2 * u53<R>(b.w[0], b.w[1]) - (R)1;
+    const R phi = (R)(2.0 * kPi) * u53<R>(b.w[2], b.w[3]);
+    const R st = m_sqrt(((R)1 - ct) * ((R)1 + ct));
+    const R a[3] = {st * m_cos(phi), st * m_sin(phi), ct};
+    const R bm[3] = {-a[0], -a[1], -a[2]};
+    uint64_t ids[2];
+    child_ids(c, t, ids);
+    add_child(o, kGamma, (R)kMe, a, ids[0]);
+    add_child(o, kGamma, (R)kMe, bm, ids[1]);
+    o.n_annih += 1;
+}
+
+// ---- PreStep: returns true when the track goes on to take a step --------
+template <class P, class R = typename P::R>
+__device__ inline bool stage_prestep(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
+{
+    if (t.vol == kOutside) {
+        o.e_escaped += (double)t.T;
+        o.status = kEscaped;
+        return false;
+    }
+    if (t.type != kGamma && t.T < (R)c.ph->t_track) {
+        o.edep += (double)t.T;
+        t.T = (R)0;
+        if (t.type == kPositron) annihilate(c, t, o);
+        o.status = kDead;
+        return false;
+    }
+    if ((long long)t.nstep >= c.ph->max_steps) {
+        o.e_killed += (double)t.T;
+        o.status = kKilled;
+        return false;
+    }
+    return true;
+}
+
+// ---- ComputeIntLen ------------------------------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>& L)
+{
+    const U4 b0 = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpStep);
+    const int m = vol_material(*c.g, t.vol);
+    L.m = m;
+    L.sa = (R)0;
+    L.stot = (R)0;
+    L.range = (R)0;
+    L.s_eloss = big_len<R>();
+    L.usel = u53<R>(b0.w[2], b0.w[3]);
+    if (m >= 0) {
+        const R* base = tab_base(c.tv, m, t.type);
+        const int i = find_bin(c.tv, t.T, c.ph->log10_emin, c.ph->bpd);
+        const R w = (t.T - c.tv.E[i]) / (c.tv.E[i + 1] - c.tv.E[i]);
+        L.sa = lerp_col(c.tv, base, i, 0, w);
+        const R sb = lerp_col(c.tv, base, i, 1, w);
+        L.stot = L.sa + sb;
+        if (t.type != kGamma) {
+            L.range = lerp_col(c.tv, base, i, 3, w);
+            L.s_eloss = L.range <= (R)0.1 ? L.range : m_max((R)0.2 * L.range, (R)0.1);
+        }
+    }
+    L.s_phys = L.stot > (R)0 ? expo<R>(b0.w[0], b0.w[1]) / L.stot : big_len<R>();
+}
+
+// ---- GeomQuery ----------------------------------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
+{
+    const double d[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
+    const Hit h = distance_out(*c.g, t.vol, t.x, d);
+    G.d_bnd = h.t;
+    G.next = h.next;
+    G.snap_axis = h.snap_axis;
+    G.snap_val = h.snap_val;
+    G.safety = safety(*c.g, t.vol, t.x);
+}
+
+// ---- Propagation --------------------------------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
+{
+    const DevGeom& g = *c.g;
+    const double s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
+    const double s_eloss = L.s_eloss >= big_len<R>() ? kInf : (double)L.s_eloss;
+    const double s_lim = fmin(s_phys, s_eloss);
+    pr.T_pre = t.T;
+    pr.crossed = 0;
+    if (t.type == kGamma || g.Bmag == 0.0) {
+        if (G.d_bnd <= s_lim) {
+            pr.s = G.d_bnd;
+            pr.lim = kLimGeom;
+        } else {
+            pr.s = s_lim;
+            pr.lim = s_phys <= s_eloss ? kLimPhys : kLimEloss;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t.x[a] += pr.s * (double)t.u[a];
+        if (pr.lim == kLimGeom) {
+            if (G.snap_axis >= 0) t.x[G.snap_axis] = G.snap_val;
+            t.vol = G.next;
+            pr.crossed = 1;
+        }
+        return;
+    }
+    // charged particle in a uniform field
+    const R p = m_sqrt(t.T * (t.T + (R)(2.0 * kMe)));
+    // sine of the pitch angle from |u x b| (no cancellation near 0 or pi)
+    const R bx = (R)(g.B[0] / g.Bmag), by = (R)(g.B[1] / g.Bmag), bz = (R)(g.B[2] / g.Bmag);
+    const R cx = t.u[1] * bz - t.u[2] * by, cy = t.u[2] * bx - t.u[0] * bz, cz = t.u[0] * by - t.u[1] * bx;
+    const R sin2 = cx * cx + cy * cy + cz * cz;
+    double rcurv = kInf, dfield = kInf;
+    if (sin2 > (R)0) {
+        const R rc = p / ((R)(kKB * g.Bmag) * m_sqrt(sin2));
+        rcurv = (double)rc;
+        dfield = (double)m_sqrt((R)2 * rc * (R)c.ph->chord_tol);
+    }
+    const double cap = fmax(dfield, G.safety);
+    const double s0 = fmin(s_lim, G.d_bnd);
+    if (s0 <= cap) {
+        pr.s = s0;
+        pr.lim = G.d_bnd <= s_lim ? kLimGeom : (s_phys <= s_eloss ? kLimPhys : kLimEloss);
+    } else {
+        pr.s = cap;
+        pr.lim = kLimField;
+    }
+    if (pr.lim == kLimGeom) pr.s += c.ph->push;
+    if (c.ph->field_method == 1) {
+        double nsub = rcurv < kInf ? ceil(pr.s / (c.ph->rk_frac * rcurv)) : 1.0;
+        nsub = nsub < 1.0 ? 1.0 : (nsub > 100000.0 ? 100000.0 : nsub);
+        rk4_move<R>(t.type, t.T, g.B, pr.s, (int)nsub, t.x, t.u);
+    } else {
+        helix_move<R>(t.type, t.T, g.B, g.Bmag, pr.s, t.x, t.u);
+    }
+    const int nv = locate(g, t.x);
+    if (nv != t.vol) {
+        t.vol = nv;
+        pr.lim = kLimGeom;
+        pr.crossed = 1;
+    }
+}
+
+// ---- PostPropagation: multiple scattering -------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void stage_msc(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Prop<R>& pr)
+{
+    if (t.type == kGamma || L.m < 0 || !(pr.s > 0.0)) return;
+    const R th0 = highland<R>(pr.T_pre, (R)pr.s, (R)c.ph->mat[L.m].X0);
+    const U4 b = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpMsc);
+    const R ua = u53<R>(b.w[0], b.w[1]), ub = u53<R>(b.w[2], b.w[3]);
+    const R r = m_sqrt((R)-2 * m_log(ua));
+    const R a = (R)(2.0 * kPi) * ub;
+    const R tx = th0 * (r * m_cos(a)), ty = th0 * (r * m_sin(a));
+    const R th = m_sqrt(tx * tx + ty * ty);
+    const R phi = m_atan2(ty, tx);
+    rotate<R>(t.u, m_cos(th), m_sin(th), phi);
+}
+
+// ---- AlongStepAction: continuous loss; returns true if the track stopped --
+template <class P, class R = typename P::R>
+__device__ inline bool stage_eloss(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Prop<R>& pr, StepOut<R>& o)
+{
+    if (t.type == kGamma || L.m < 0) return false;
+    const R* base = tab_base(c.tv, L.m, t.type);
+    const R Tp = pr.T_pre;
+    const R s = (R)pr.s;
+    R dE;
+    if (s < (R)0.01 * L.range) {
+        const int i = find_bin(c.tv, Tp, c.ph->log10_emin, c.ph->bpd);
+        const R w = (Tp - c.tv.E[i]) / (c.tv.E[i + 1] - c.tv.E[i]);
+        dE = lerp_col(c.tv, base, i, 2, w) * s;
+    } else {
+        dE = Tp - range_inverse(c.tv, base, L.range - s);
+    }
+    const R rtrack = P::kMixed ? (R)c.ph->r_track_f[L.m][t.type == kPositron] : (R)c.ph->r_track[L.m][t.type == kPositron];
+    bool stopped = false;
+    if (Tp - dE < (R)c.ph->t_track || L.range - s <= rtrack) {
+        dE = Tp;
+        stopped = true;
+    }
+    o.edep += (double)dE;
+    t.T = Tp - dE;
+    return stopped;
+}
+
+// ---- PostStepActions: discrete interaction ------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void interact(const Ctx<P>& c, Track<P>& t, bool first, StepOut<R>& o)
+{
+    const DevPhys& ph = *c.ph;
+    const Key key{c.seed, t.tid, t.ev, t.nstep};
+    uint64_t ids[2];
+    if (t.type == kGamma) {
+        const R k = t.T;
+        if (first) {
+            o.proc = kCompton;
+            R eps, om, tt, phi;
+            if (!sample_compton<R>(k, key, eps, om, tt, phi)) o.rej_exhausted += 1;
+            const R k1 = eps * k, Te = om * k;
+            const R st = m_sqrt(tt * ((R)2 - tt));
+            R de[3] = {t.u[0], t.u[1], t.u[2]};
+            rotate<R>(t.u, (R)1 - tt, st, phi);
+            child_ids(c, t, ids);
+            if (Te >= (R)ph.t_track) {
+                // electron momentum k u - k' u' = (Te + k' t) u - k' sin(theta) n:
+                // polar angle atan2(k' sin, Te + k' t) on the opposite azimuth
+                const R A = Te + k1 * tt, Bv = k1 * st;
+                const R N = m_sqrt(A * A + Bv * Bv);
+                rotate<R>(de, A / N, Bv / N, phi + (R)kPi);
+                add_child(o, kElectron, Te, de, ids[0]);
+            } else {
+                o.edep += (double)Te;
+            }
+            if (k1 < (R)ph.t_track) {
+                o.edep += (double)k1;
+                t.T = (R)0;
+                o.status = kDead;
+            } else {
+                t.T = k1;
+            }
+        } else {
+            if (k <= (R)(2.0 * kMe)) {
+                o.proc = kNull;
+                return;
+            }
+            o.proc = kPair;
+            R x, phi;
+            if (!sample_pair<R>(k, key, x, phi)) o.rej_exhausted += 1;
+            const R Em = x * k, Ep = ((R)1 - x) * k;
+            const R thm = (R)kMe / Em, thp = (R)kMe / Ep;
+            R dm[3] = {t.u[0], t.u[1], t.u[2]};
+            R dp[3] = {t.u[0], t.u[1], t.u[2]};
+            rotate<R>(dm, m_cos(thm), m_sin(thm), phi);
+            rotate<R>(dp, m_cos(thp), m_sin(thp), phi + (R)kPi);
+            child_ids(c, t, ids);
+            const R Tm = Em - (R)kMe, Tq = Ep - (R)kMe;
+            if (Tm >= (R)ph.t_track) add_child(o, kElectron, Tm, dm, ids[0]);
+            else o.edep += (double)Tm;
+            add_child(o, kPositron, Tq, dp, ids[1]);
+            o.n_pair += 1;
+            t.T = (R)0;
+            o.status = kDead;
+        }
+        return;
+    }
+    const R T = t.T;
+    if (first) {
+        const bool pos = t.type == kPositron;
+        if (pos ? T <= (R)ph.t_cut : T <= (R)(2.0 * ph.t_cut)) {
+            o.proc = kNull;
+            return;
+        }
+        o.proc = pos ? kBhabha : kMoller;
+        R eps, phi;
+        const bool ok = pos ? sample_bhabha<R>(T, (R)ph.t_cut, key, eps, phi)
+                            : sample_moller<R>(T, (R)ph.t_cut, key, eps, phi);
+        if (!ok) o.rej_exhausted += 1;
+        const R Td = eps * T;
+        const R Tp = T - Td;
+        const R m2 = (R)(2.0 * kMe);
+        // two-body kinematics on an electron at rest (equal masses): each
+        // outgoing particle of kinetic energy T_o leaves at
+        // cos = sqrt(T_o (T + 2m) / (T (T_o + 2m))); the two azimuths are opposite
+        const R ct = m_sqrt(Td * (T + m2) / (T * (Td + m2)));
+        const R st = m_sqrt(m2 * Tp / (T * (Td + m2)));
+        R ud[3] = {t.u[0], t.u[1], t.u[2]};
+        rotate<R>(ud, ct, st, phi);
+        child_ids(c, t, ids);
+        add_child(o, kElectron, Td, ud, ids[0]);
+        if (Tp > (R)0) {
+            const R cp = m_sqrt(Tp * (T + m2) / (T * (Tp + m2)));
+            const R sp = m_sqrt(m2 * Td / (T * (Tp + m2)));
+            rotate<R>(t.u, cp, sp, phi + (R)kPi);
+        }
+        t.T = Tp;
+    } else {
+        if (T <= (R)ph.k_cut) {
+            o.proc = kNull;
+            return;
+        }
+        o.proc = t.type == kPositron ? kBremsEp : kBremsEm;
+        R k;
+        if (!sample_brems<R>(T, (R)ph.k_cut, key, k)) o.rej_exhausted += 1;
+        child_ids(c, t, ids);
+        add_child(o, kGamma, k, t.u, ids[0]);
+        t.T = T - k;
+    }
+}
+
+// ---- PostStepActions + SteppingActions ----------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void stage_finish(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Prop<R>& pr, bool stopped,
+                                    StepOut<R>& o)
+{
+    if (pr.lim == kLimPhys && !pr.crossed && !stopped) interact(c, t, L.usel * L.stot < L.sa, o);
+    if (stopped) {
+        if (t.type == kPositron) annihilate(c, t, o);
+        o.status = kDead;
+    } else if (o.status == kAlive && t.vol == kOutside) {
+        o.e_escaped += (double)t.T;
+        o.status = kEscaped;
+    }
+    t.nstep += 1;
+}
+
+// ---- the whole step in registers ----------------------------------------
+template <class P, class R = typename P::R>
+__device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
+{
+    init_out(t, o);
+    if (!stage_prestep(c, t, o)) return;
+    Limits<R> L;
+    stage_limit(c, t, L);
+    Geo G;
+    stage_geom(c, t, G);
+    Prop<R> pr;
+    stage_move(c, t, L, G, pr);
+    o.did_step = 1;
+    o.s = pr.s;
+    o.lim = pr.lim;
+    o.s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
+    o.d_bnd = G.d_bnd;
+    o.safety = G.safety;
+    stage_msc(c, t, L, pr);
+    const bool stopped = stage_eloss(c, t, L, pr, o);
+    stage_finish(c, t, L, pr, stopped, o);
+}
+
+}  // namespace gv
