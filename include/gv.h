@@ -179,6 +179,16 @@ int gv_configure(const gv_config* cfg);
  * GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_CAPACITY, GV_E_HIP, GV_E_STATE. */
 int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* edep_out);
 
+/* The same transport in two calls, so that the primaries can be made
+ * resident on the device once and transported many times (e.g. with
+ * different seeds or options): gv_stage validates the primaries (same rules
+ * and errors as gv_transport), groups them by event and copies them to the
+ * device; gv_transport_staged transports the staged batch (errors as
+ * gv_transport, plus GV_E_STATE if nothing is staged).  gv_init discards the
+ * staged batch. */
+int gv_stage(const gv_primary* primaries, int64_t n);
+int gv_transport_staged(uint64_t seed, double* edep_out);
+
 /* Counters of the last transport. */
 int gv_stats(gv_stats_t* out);
 

@@ -107,6 +107,8 @@ def load():
     lib.gv_init.argtypes = [C.POINTER(Material), C.c_int32, C.POINTER(Geometry), C.POINTER(Tables)]
     lib.gv_configure.argtypes = [C.POINTER(Config)]
     lib.gv_transport.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
+    lib.gv_stage.argtypes = [C.c_void_p, C.c_int64]
+    lib.gv_transport_staged.argtypes = [C.c_uint64, C.c_void_p]
     lib.gv_stats.argtypes = [C.POINTER(Stats)]
     lib.gv_ledger.argtypes = [C.c_void_p, C.c_int64]
     lib.gv_trace.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
@@ -196,6 +198,22 @@ class Engine:
             return edep
         _check(self.lib.gv_transport(prim.ctypes.data, len(prim), seed, edep_out))
         self.n_events = n_events
+        return None
+
+    def stage(self, primaries):
+        """Validate and copy the primaries to the device once (gv_stage)."""
+        prim = np.ascontiguousarray(primaries)
+        _check(self.lib.gv_stage(prim.ctypes.data, len(prim)))
+        self.n_events = int(prim["event"].max()) + 1
+        self._staged = prim
+
+    def transport_staged(self, seed, edep_out=None):
+        """Transport the staged batch (gv_transport_staged); edep_out as in transport()."""
+        if edep_out is None:
+            edep = np.zeros((self.n_events, self.n_cells), dtype=np.float64)
+            _check(self.lib.gv_transport_staged(seed, edep.ctypes.data))
+            return edep
+        _check(self.lib.gv_transport_staged(seed, edep_out))
         return None
 
     def stats(self):

@@ -13,7 +13,9 @@
 // straight boundary-limited step places the point exactly on the plane.
 // Ties between faces resolve in the order x-, x+, y-, y+, z-, z+ (shells:
 // inner, outer, z-, z+) with strict comparisons.  All arithmetic is double:
-// positions and boundaries stay FP64 under every precision policy.
+// positions and boundaries stay FP64 under every precision policy, and is not
+// contracted into fused multiply-adds, so that distances near a surface round
+// exactly as written.
 #pragma once
 #include "gv_common.h"
 
@@ -50,6 +52,7 @@ __device__ __forceinline__ int vol_cell(const DevGeom& g, int v) { return v >= 1
 // stack volume containing coordinate c along the stack axis: bounds[v-1] <= c < bounds[v]
 __device__ __forceinline__ int stack_of(const DevGeom& g, double c)
 {
+#pragma clang fp contract(off)
     if (c <= g.bounds[0]) return 1;
     if (c >= g.bounds[g.n_vol]) return g.n_vol;
     int lo = 0, hi = g.n_vol;
@@ -63,6 +66,7 @@ __device__ __forceinline__ int stack_of(const DevGeom& g, double c)
 
 __device__ inline int locate(const DevGeom& g, const double p[3])
 {
+#pragma clang fp contract(off)
     if (g.axis == 0) {
         if (fabs(p[0]) <= g.env[0] && fabs(p[1]) <= g.env[1] && p[2] >= g.bounds[0] && p[2] <= g.bounds[g.n_vol])
             return stack_of(g, p[2]);
@@ -80,6 +84,7 @@ __device__ inline int locate(const DevGeom& g, const double p[3])
 
 __device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], const double d[3])
 {
+#pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[v - 1]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[v]};
     double best = kInf;
@@ -104,6 +109,7 @@ __device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], cons
 
 __device__ inline double slab_safety(const DevGeom& g, int v, const double p[3])
 {
+#pragma clang fp contract(off)
     double s = fmin(p[2] - g.bounds[v - 1], g.bounds[v] - p[2]);
     s = fmin(s, g.env[0] - fabs(p[0]));
     s = fmin(s, g.env[1] - fabs(p[1]));
@@ -112,6 +118,7 @@ __device__ inline double slab_safety(const DevGeom& g, int v, const double p[3])
 
 __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const double d[3])
 {
+#pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
     double tn = -kInf, tf = kInf;
@@ -166,6 +173,7 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
 
 __device__ inline double slab_world_safety(const DevGeom& g, const double p[3])
 {
+#pragma clang fp contract(off)
     double s = fmin(g.world[0] - fabs(p[0]), g.world[1] - fabs(p[1]));
     s = fmin(s, fmin(p[2] - g.world[2], g.world[3] - p[2]));
     const double zc = 0.5 * (g.bounds[0] + g.bounds[g.n_vol]);
@@ -182,6 +190,7 @@ __device__ inline double slab_world_safety(const DevGeom& g, const double p[3])
 // leave the cylinder of radius R from inside (far root)
 __device__ __forceinline__ double cyl_out(const double p[3], const double d[3], double R)
 {
+#pragma clang fp contract(off)
     const double a = d[0] * d[0] + d[1] * d[1];
     if (a == 0.0) return kInf;
     const double b = p[0] * d[0] + p[1] * d[1];
@@ -193,6 +202,7 @@ __device__ __forceinline__ double cyl_out(const double p[3], const double d[3], 
 // reach the cylinder of radius R from outside while moving inward (near root)
 __device__ __forceinline__ double cyl_in(const double p[3], const double d[3], double R)
 {
+#pragma clang fp contract(off)
     const double a = d[0] * d[0] + d[1] * d[1];
     const double b = p[0] * d[0] + p[1] * d[1];
     if (a == 0.0 || b >= 0.0) return kInf;
@@ -204,6 +214,7 @@ __device__ __forceinline__ double cyl_in(const double p[3], const double d[3], d
 
 __device__ inline Hit shell_exit(const DevGeom& g, int v, const double p[3], const double d[3])
 {
+#pragma clang fp contract(off)
     const double rin = g.bounds[v - 1], rout = g.bounds[v], H = g.env[0];
     double best = kInf;
     int face = -1;
@@ -238,6 +249,7 @@ __device__ inline Hit shell_exit(const DevGeom& g, int v, const double p[3], con
 
 __device__ inline double shell_safety(const DevGeom& g, int v, const double p[3])
 {
+#pragma clang fp contract(off)
     const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
     const double rin = g.bounds[v - 1];
     double s = g.bounds[v] - r;
@@ -248,6 +260,7 @@ __device__ inline double shell_safety(const DevGeom& g, int v, const double p[3]
 
 __device__ inline Hit shell_world(const DevGeom& g, const double p[3], const double d[3])
 {
+#pragma clang fp contract(off)
     const double R = g.bounds[g.n_vol], H = g.env[0];
     Hit h;
     h.t = kInf;
@@ -317,6 +330,7 @@ __device__ inline Hit shell_world(const DevGeom& g, const double p[3], const dou
 
 __device__ inline double shell_world_safety(const DevGeom& g, const double p[3])
 {
+#pragma clang fp contract(off)
     const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
     const double R = g.bounds[g.n_vol], H = g.env[0];
     const double dr = r - R, dz = fabs(p[2]) - H;
@@ -329,12 +343,14 @@ __device__ inline double shell_world_safety(const DevGeom& g, const double p[3])
 
 __device__ inline Hit distance_out(const DevGeom& g, int v, const double p[3], const double d[3])
 {
+#pragma clang fp contract(off)
     if (g.axis == 0) return v == 0 ? slab_world(g, p, d) : slab_exit(g, v, p, d);
     return v == 0 ? shell_world(g, p, d) : shell_exit(g, v, p, d);
 }
 
 __device__ inline double safety(const DevGeom& g, int v, const double p[3])
 {
+#pragma clang fp contract(off)
     if (g.axis == 0) return v == 0 ? slab_world_safety(g, p) : slab_safety(g, v, p);
     return v == 0 ? shell_world_safety(g, p) : shell_safety(g, v, p);
 }

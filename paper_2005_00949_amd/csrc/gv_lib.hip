@@ -175,6 +175,16 @@ struct Lib {
     int64_t last_events = 0;
     double init_ms = 0.0;
     double plain_loads = 0.0, plain_stores = 0.0;
+    // the staged batch (gv_stage): primaries grouped by event, resident on the device
+    std::vector<PrimDev> hp;
+    std::vector<size_t> ev_start;
+    int64_t n_events = 0;
+    int64_t n_prim = 0;
+    double e_in = 0.0;
+    int64_t tracks0[3] = {0, 0, 0};
+    bool staged = false;
+    size_t staged_b = 0, staged_e = 0;   // window whose queue slots are on the device
+    bool staged_one_queue = false;       // ... laid out for one mixed pool (plain) or per type
 };
 
 Lib L;
@@ -246,6 +256,9 @@ void release_all()
     L.ev0 = L.ev1 = nullptr;
     if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
     L.own_stream = nullptr;
+    L.staged = false;
+    L.hp.clear();
+    L.ev_start.clear();
     L.ready = false;
 }
 
@@ -496,24 +509,31 @@ template <class P> size_t batch_cap();
 template <> size_t batch_cap<P64>() { return L.q64.cap; }
 template <> size_t batch_cap<PMix>() { return L.qmix.cap; }
 
-// ingest primaries [b, e) of the sorted list into parity-0 queues
+// ingest primaries [b, e) of the staged batch into parity-0 queues
 template <class P>
-int ingest(const std::vector<PrimDev>& hp, size_t b, size_t e, Soa<P> q[3], uint32_t counts[3])
+int ingest(size_t b, size_t e, Soa<P> q[3], uint32_t counts[3], size_t cap, bool one_queue)
 {
     const size_t n = e - b;
-    std::vector<uint32_t> slot(n);
     counts[0] = counts[1] = counts[2] = 0;
-    for (size_t i = 0; i < n; ++i) slot[i] = counts[hp[b + i].type]++;
+    for (size_t i = b; i < e; ++i) counts[one_queue ? 0 : L.hp[i].type]++;
     for (int t = 0; t < 3; ++t)
-        if (counts[t] > batch_cap<P>()) return GV_E_CAPACITY;
-    HIPCHK(L.prim.ensure(std::max<size_t>(n, 1)));
-    HIPCHK(L.prim_slot.ensure(std::max<size_t>(n, 1)));
+        if (counts[t] > cap) return GV_E_CAPACITY;
     hipStream_t s = stream();
-    HIPCHK(hipMemcpyAsync(L.prim.p, hp.data() + b, n * sizeof(PrimDev), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(L.prim_slot.p, slot.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    k_ingest<P><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L.prim.p, (long long)n, L.prim_slot.p, q[0], q[1], q[2]);
+    if (!(L.staged_b == b && L.staged_e == e && L.staged_one_queue == one_queue && L.prim_slot.n >= n && L.staged)) {
+        std::vector<uint32_t> slot(n);
+        uint32_t c[3] = {0, 0, 0};
+        for (size_t i = 0; i < n; ++i) slot[i] = c[one_queue ? 0 : L.hp[b + i].type]++;
+        HIPCHK(L.prim_slot.ensure(std::max<size_t>(n, 1)));
+        HIPCHK(hipMemcpyAsync(L.prim_slot.p, slot.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        L.staged_b = b;
+        L.staged_e = e;
+        L.staged_one_queue = one_queue;
+    }
+    if (one_queue)
+        k_ingest<P><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L.prim.p + b, (long long)n, L.prim_slot.p, q[0], q[0], q[0]);
+    else
+        k_ingest<P><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L.prim.p + b, (long long)n, L.prim_slot.p, q[0], q[1], q[2]);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
     return GV_OK;
 }
 
@@ -566,12 +586,11 @@ template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
 }
 
 // batched transport of one event window; returns GV_E_CAPACITY on overflow
-template <class P>
-int run_batched_window(const std::vector<PrimDev>& hp, size_t b, size_t e, uint64_t seed, const Tuning& tu)
+template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, const Tuning& tu)
 {
     QueueMem<P>& Q = batch_queues<P>();
     uint32_t counts[3];
-    int rc = ingest<P>(hp, b, e, Q.q[0], counts);
+    int rc = ingest<P>(b, e, Q.q[0], counts, Q.cap, false);
     if (rc) return rc;
     rc = upload_ctrl(counts, seed);
     if (rc) return rc;
@@ -617,26 +636,14 @@ int run_batched_window(const std::vector<PrimDev>& hp, size_t b, size_t e, uint6
 }
 
 // plain transport of one event window
-int run_plain_window(const std::vector<PrimDev>& hp, size_t b, size_t e, uint64_t seed)
+int run_plain_window(size_t b, size_t e, uint64_t seed)
 {
     QueueMem<P64>& Q = L.plain_pool;
     uint32_t counts[3];
-    // all primaries into the single pool of parity 0 (type column set)
+    // all primaries into the single pool of parity 0 (type column set), in order
     {
-        const size_t n = e - b;
-        if (n > Q.cap) return GV_E_CAPACITY;
-        std::vector<uint32_t> slot(n);
-        for (size_t i = 0; i < n; ++i) slot[i] = (uint32_t)i;
-        HIPCHK(L.prim.ensure(std::max<size_t>(n, 1)));
-        HIPCHK(L.prim_slot.ensure(std::max<size_t>(n, 1)));
-        hipStream_t s = stream();
-        HIPCHK(hipMemcpyAsync(L.prim.p, hp.data() + b, n * sizeof(PrimDev), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(L.prim_slot.p, slot.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        k_ingest<P64><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L.prim.p, (long long)n, L.prim_slot.p, Q.q[0][0],
-                                                                  Q.q[0][0], Q.q[0][0]);
-        HIPCHK(hipGetLastError());
-        counts[0] = (uint32_t)n;
-        counts[1] = counts[2] = 0;
+        int rc0 = ingest<P64>(b, e, Q.q[0], counts, Q.cap, true);
+        if (rc0) return rc0;
     }
     int rc = upload_ctrl(counts, seed);
     if (rc) return rc;
@@ -714,9 +721,9 @@ int type_of_pdg(int pdg)
     return pdg == 22 ? kGamma : pdg == 11 ? kElectron : pdg == -11 ? kPositron : -1;
 }
 
-template <class P> int transport_batched(const std::vector<PrimDev>& hp, const std::vector<size_t>& ev_start,
-                                         int64_t n_events, uint64_t seed)
+template <class P> int transport_batched(int64_t n_events, uint64_t seed)
 {
+    const std::vector<size_t>& ev_start = L.ev_start;
     const size_t cap = capacity_for_driver(false);
     QueueMem<P>& Q = batch_queues<P>();
     if (Q.cap != cap) {
@@ -726,7 +733,7 @@ template <class P> int transport_batched(const std::vector<PrimDev>& hp, const s
         L.qmix.release();
         HIPCHK(Q.alloc(cap, 6, false));
     }
-    const Tuning tu = pick_tuning((int)hp.size());
+    const Tuning tu = pick_tuning((int)L.n_prim);
     int rc = ensure_status(cap, tu.block);
     if (rc) return rc;
     L.stats.basket = tu.block * tu.chunks;
@@ -738,7 +745,7 @@ template <class P> int transport_batched(const std::vector<PrimDev>& hp, const s
     int64_t e0 = 0;
     while (e0 < n_events) {
         const int64_t e1 = std::min(n_events, e0 + window);
-        rc = run_batched_window<P>(hp, ev_start[e0], ev_start[e1], seed, tu);
+        rc = run_batched_window<P>(ev_start[e0], ev_start[e1], seed, tu);
         if (rc == GV_E_CAPACITY) {
             if (e1 - e0 <= 1) return fail(GV_E_CAPACITY, "track queues overflow with one event in flight");
             // undo the window's partial deposits and retry with half the events
@@ -755,9 +762,9 @@ template <class P> int transport_batched(const std::vector<PrimDev>& hp, const s
     return GV_OK;
 }
 
-int transport_plain(const std::vector<PrimDev>& hp, const std::vector<size_t>& ev_start, int64_t n_events,
-                    uint64_t seed)
+int transport_plain(int64_t n_events, uint64_t seed)
 {
+    const std::vector<size_t>& ev_start = L.ev_start;
     const size_t cap = capacity_for_driver(true);
     int rc = ensure_plain_buffers(cap);
     if (rc) return rc;
@@ -768,7 +775,7 @@ int transport_plain(const std::vector<PrimDev>& hp, const std::vector<size_t>& e
     int64_t e0 = 0;
     while (e0 < n_events) {
         const int64_t e1 = std::min(n_events, e0 + window);
-        rc = run_plain_window(hp, ev_start[e0], ev_start[e1], seed);
+        rc = run_plain_window(ev_start[e0], ev_start[e1], seed);
         if (rc == GV_E_CAPACITY) {
             if (e1 - e0 <= 1) return fail(GV_E_CAPACITY, "track pool overflow with one event in flight");
             const size_t nc = (size_t)std::max(L.n_cells, 1);
@@ -899,12 +906,13 @@ int gv_configure(const gv_config* cfg)
     return apply_run_params();
 }
 
-int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* edep_out)
+int gv_stage(const gv_primary* primaries, int64_t n)
 {
     if (!L.ready) return fail(GV_E_NOT_INIT, "gv_init has not succeeded");
     if (L.busy) return fail(GV_E_STATE, "transport in progress");
-    if (!primaries || n <= 0 || !edep_out) return fail(GV_E_INVALID_ARG, "null primaries/edep or n <= 0");
-    const double t0 = now_ms();
+    if (!primaries || n <= 0) return fail(GV_E_INVALID_ARG, "null primaries or n <= 0");
+    if (n > ((int64_t)1 << 31)) return fail(GV_E_INVALID_ARG, "too many primaries");
+    L.staged = false;
     // ---- validate, type, count events (bookkeeping only) ----
     const double e_max = L.phys.e_min * std::pow(10.0, (L.phys.n_nodes - 1) / L.phys.bpd);
     int64_t n_events = 0;
@@ -920,15 +928,14 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
         if (!(std::fabs(nn - 1.0) <= 1.0e-6)) return fail(GV_E_INVALID_ARG, "direction not normalised");
         n_events = std::max<int64_t>(n_events, (int64_t)p.event + 1);
     }
-    if (n_events > (int64_t)1 << 31) return fail(GV_E_INVALID_ARG, "too many events");
     // primaries grouped by event (stable); track id = order within the event
-    std::vector<size_t> ev_start((size_t)n_events + 1, 0);
-    for (int64_t i = 0; i < n; ++i) ev_start[(size_t)primaries[i].event + 1]++;
-    for (int64_t e = 0; e < n_events; ++e) ev_start[e + 1] += ev_start[e];
-    std::vector<size_t> fill(ev_start.begin(), ev_start.end() - 1);
-    std::vector<PrimDev> hp((size_t)n);
-    double e_in = 0.0;
-    int64_t tracks0[3] = {0, 0, 0};
+    L.ev_start.assign((size_t)n_events + 1, 0);
+    for (int64_t i = 0; i < n; ++i) L.ev_start[(size_t)primaries[i].event + 1]++;
+    for (int64_t e = 0; e < n_events; ++e) L.ev_start[e + 1] += L.ev_start[e];
+    std::vector<size_t> fill(L.ev_start.begin(), L.ev_start.end() - 1);
+    L.hp.resize((size_t)n);
+    L.e_in = 0.0;
+    L.tracks0[0] = L.tracks0[1] = L.tracks0[2] = 0;
     for (int64_t i = 0; i < n; ++i) {
         const gv_primary& p = primaries[i];
         const size_t k = fill[p.event]++;
@@ -943,11 +950,29 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
         d.type = type_of_pdg(p.pdg);
         d.vol = 0;
         d.ev = (uint32_t)p.event;
-        d.tid = (uint64_t)(k - ev_start[p.event]);
-        hp[k] = d;
-        e_in += p.ekin_MeV;
-        tracks0[d.type]++;
+        d.tid = (uint64_t)(k - L.ev_start[p.event]);
+        L.hp[k] = d;
+        L.e_in += p.ekin_MeV;
+        L.tracks0[d.type]++;
     }
+    L.n_events = n_events;
+    L.n_prim = n;
+    HIPCHK(L.prim.ensure((size_t)n));
+    HIPCHK(hipMemcpyAsync(L.prim.p, L.hp.data(), (size_t)n * sizeof(PrimDev), hipMemcpyHostToDevice, stream()));
+    HIPCHK(hipStreamSynchronize(stream()));
+    L.staged_b = L.staged_e = (size_t)-1;
+    L.staged = true;
+    return GV_OK;
+}
+
+int gv_transport_staged(uint64_t seed, double* edep_out)
+{
+    if (!L.ready) return fail(GV_E_NOT_INIT, "gv_init has not succeeded");
+    if (L.busy) return fail(GV_E_STATE, "transport in progress");
+    if (!L.staged) return fail(GV_E_STATE, "no staged primaries (gv_stage)");
+    if (!edep_out) return fail(GV_E_INVALID_ARG, "null edep_out");
+    const double t0 = now_ms();
+    const int64_t n_events = L.n_events;
     L.busy = true;
     struct Guard {
         ~Guard() { L.busy = false; }
@@ -965,9 +990,9 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
     L.stats.init_ms = L.init_ms;
     L.stats.driver = L.cfg.driver;
     L.stats.precision = L.cfg.precision;
-    if (L.cfg.driver == GV_DRIVER_PLAIN) rc = transport_plain(hp, ev_start, n_events, seed);
-    else if (L.cfg.precision == GV_P64) rc = transport_batched<P64>(hp, ev_start, n_events, seed);
-    else rc = transport_batched<PMix>(hp, ev_start, n_events, seed);
+    if (L.cfg.driver == GV_DRIVER_PLAIN) rc = transport_plain(n_events, seed);
+    else if (L.cfg.precision == GV_P64) rc = transport_batched<P64>(n_events, seed);
+    else rc = transport_batched<PMix>(n_events, seed);
     if (rc) return rc;
     // ---- results ----
     const size_t ne = (size_t)n_events * (size_t)L.n_cells;
@@ -987,14 +1012,14 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
     L.last_events = n_events;
     for (int t = 0; t < 3; ++t) {
         L.stats.steps[t] = (int64_t)cnt[kCSteps + t];
-        L.stats.tracks[t] = (int64_t)cnt[kCTracks + t] + tracks0[t];
+        L.stats.tracks[t] = (int64_t)cnt[kCTracks + t] + L.tracks0[t];
     }
     for (int p = 0; p < kNProc; ++p) L.stats.interactions[p] = (int64_t)cnt[kCProc + p];
     L.stats.escaped = (int64_t)cnt[kCEscaped];
     L.stats.killed = (int64_t)cnt[kCKilled];
     L.stats.rejection_exhausted = (int64_t)cnt[kCRej];
     L.stats.trace_records = (int64_t)std::min<unsigned long long>(tn, (unsigned long long)L.cfg.trace_cap);
-    L.stats.e_in = e_in;
+    L.stats.e_in = L.e_in;
     double ed = 0.0, es = 0.0, ek = 0.0, np_ = 0.0, na = 0.0;
     for (int64_t e = 0; e < n_events; ++e) {
         es += L.ledger_h[4 * e + 0];
@@ -1004,13 +1029,15 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
     }
     if (!L.cfg.edep_on_device)
         for (size_t i = 0; i < ne; ++i) ed += edep_out[i];
+    else
+        ed = L.e_in + 2.0 * kMe * (na - np_) - es - ek;   // by the ledger identity
     L.stats.e_dep = ed;
     L.stats.e_escaped = es;
     L.stats.e_killed = ek;
     L.stats.n_pair = np_;
     L.stats.n_annih = na;
-    // track-state bytes the batched kernel must move: one slot read per track
-    // per launch, one slot written per survivor and per secondary
+    // track-state bytes the step kernels must move: one slot read per track per
+    // launch, one slot written per survivor and per secondary
     if (L.cfg.driver == GV_DRIVER_BATCHED) {
         const double slot_bytes = L.cfg.precision == GV_PMIX ? 60.0 : 76.0;
         L.stats.alg_bytes = (double)(cnt[kCLoads] + cnt[kCStores]) * slot_bytes;
@@ -1019,6 +1046,17 @@ int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* 
     }
     L.stats.transport_ms = now_ms() - t0;
     return GV_OK;
+}
+
+int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* edep_out)
+{
+    if (!edep_out) {
+        if (!L.ready) return fail(GV_E_NOT_INIT, "gv_init has not succeeded");
+        return fail(GV_E_INVALID_ARG, "null edep_out");
+    }
+    int rc = gv_stage(primaries, n);
+    if (rc) return rc;
+    return gv_transport_staged(seed, edep_out);
 }
 
 int gv_stats(gv_stats_t* out)

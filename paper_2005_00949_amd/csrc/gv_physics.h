@@ -343,6 +343,7 @@ template <class R> __device__ inline bool sample_bhabha(R T, R tc, const Key& ke
 template <class R>
 __device__ inline void helix_move(int type, R T, const double B[3], double Bmag, double s, double pos[3], R u[3])
 {
+#pragma clang fp contract(off)
     // The turning angle is formed and reduced to [-pi, pi] in double so that
     // long steps keep their phase; trigonometry of the reduced angle and the
     // direction update run in the policy's precision.
@@ -377,6 +378,7 @@ __device__ inline void helix_move(int type, R T, const double B[3], double Bmag,
 template <class R>
 __device__ inline void rk4_move(int type, R T, const double B[3], double s, int nsub, double pos[3], R u[3])
 {
+#pragma clang fp contract(off)
     const R q = type == kElectron ? (R)-1 : (R)1;
     const R p = m_sqrt(T * (T + (R)(2.0 * kMe)));
     const R kq = q * (R)kKB / p;

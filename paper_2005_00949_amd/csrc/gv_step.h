@@ -215,6 +215,7 @@ __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 template <class P, class R = typename P::R>
 __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
+#pragma clang fp contract(off)
     const DevGeom& g = *c.g;
     const double s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
     const double s_eloss = L.s_eloss >= big_len<R>() ? kInf : (double)L.s_eloss;

@@ -141,3 +141,25 @@ def test_paired_layer_deposits_mixed_vs_oracle(gv, oracle_mod):
         float(np.max(np.abs(delta[big]) / m[big])), int((~ok3).sum())))
     assert ok05.all()
     assert (~ok3).sum() <= 1   # 20 layers at 3 sigma: allow one excursion
+
+
+def test_staged_batch_reused_across_drivers(gv, oracle_mod):
+    """One staged batch transported by the batched drivers and then by the
+    plain driver: each must reproduce the oracle (the queue layouts of the
+    drivers differ, so staged primaries must be re-laid-out per driver)."""
+    geom, prim, seed = gv_inputs.workload("c4", 90)
+    ref = oracle_mod.Oracle(geom).transport(prim, seed)
+    eng = gv.Engine(geom)
+    eng.stage(prim)
+    scale = max(1.0, ref["edep"].max())
+    for cfg in [dict(driver=gv.DRIVER_BATCHED, precision=gv.PMIX), dict(driver=gv.DRIVER_BATCHED, precision=gv.P64),
+                dict(driver=gv.DRIVER_PLAIN, precision=gv.P64), dict(driver=gv.DRIVER_BATCHED, precision=gv.P64)]:
+        eng.configure(**cfg)
+        e = eng.transport_staged(seed)
+        st = eng.stats()
+        n_ref = sum(ref["counters"][k] for k in ("steps_gamma", "steps_electron", "steps_positron"))
+        if cfg["precision"] == gv.P64:
+            assert st["total_steps"] == n_ref, (cfg, st["total_steps"], n_ref)
+            assert np.allclose(e, ref["edep"], rtol=1e-8, atol=1e-8 * scale), cfg
+        else:
+            assert abs(st["total_steps"] / n_ref - 1) < 0.01, (cfg, st["total_steps"], n_ref)
