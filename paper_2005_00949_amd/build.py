@@ -24,6 +24,8 @@ def flags(debug: bool = False):
     f = ["-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-O3",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # float division and square root to within a few ulp (double stays IEEE)
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", os.path.join(HERE, "..", "include")]
     if debug:

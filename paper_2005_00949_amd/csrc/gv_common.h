@@ -48,27 +48,30 @@ struct PMix {
     static constexpr bool kMixed = true;
 };
 
-// overloaded device math so that stage code is written once per policy
+// Overloaded device math so that stage code is written once per policy.  The
+// double versions are the accurate library functions; the float versions use
+// the gfx950 hardware transcendentals (log2/exp2/sin/cos units, a few ulp),
+// which keep every single-step output within its 1e-5 budget.
 __device__ __forceinline__ double m_log(double x) { return log(x); }
-__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ float m_log(float x) { return __logf(x); }
 __device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
 __device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double m_sin(double x) { return sin(x); }
-__device__ __forceinline__ float m_sin(float x) { return sinf(x); }
+__device__ __forceinline__ float m_sin(float x) { return __sinf(x); }
 __device__ __forceinline__ double m_cos(double x) { return cos(x); }
-__device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ float m_cos(float x) { return __cosf(x); }
 __device__ __forceinline__ double m_atan2(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float m_atan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
-__device__ __forceinline__ float m_pow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ float m_pow(float x, float y) { return __powf(x, y); }
 __device__ __forceinline__ double m_log10(double x) { return log10(x); }
-__device__ __forceinline__ float m_log10(float x) { return log10f(x); }
+__device__ __forceinline__ float m_log10(float x) { return __log10f(x); }
 __device__ __forceinline__ double m_floor(double x) { return floor(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
 __device__ __forceinline__ double m_min(double a, double b) { return fmin(a, b); }

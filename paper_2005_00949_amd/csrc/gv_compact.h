@@ -9,10 +9,11 @@
 //   1. per wave: ballot + popcount of the two bits of each thread's per-queue
 //      count (0..3) gives the wave-exclusive offset and the wave total;
 //   2. per block: wave totals through LDS;
-//   3. across blocks: single-pass decoupled look-back over the chunk index
-//      (chunks are claimed in increasing order, so every predecessor is owned
-//      by a resident workgroup); status words carry an epoch so they never
-//      need clearing between launches.
+//   3. across blocks: single-pass decoupled look-back over the chunk index,
+//      one wave reading 64 predecessors per round (chunks are claimed in
+//      increasing order, so every predecessor is owned by a running
+//      workgroup); status words carry an epoch so they never need clearing
+//      between launches.
 #pragma once
 #include "gv_common.h"
 
@@ -20,6 +21,9 @@ namespace gv {
 
 // status word: [epoch:30 | flag:2 | value:32]; flag 1 = aggregate, 2 = inclusive prefix
 constexpr uint64_t kFlagAgg = 1ull, kFlagInc = 2ull;
+// bound on the polls of one look-back window (each poll sleeps ~64 cycles);
+// past it the error flag is raised and the launch completes with a wrong count
+constexpr uint32_t kMaxSpins = 1u << 22;
 __device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint64_t flag, uint32_t v)
 {
     return ((uint64_t)epoch << 34) | (flag << 32) | v;
@@ -61,42 +65,77 @@ __device__ __forceinline__ void block_scan3(const int cnt[3], int excl[3], int t
     }
 }
 
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
+    return v;
+}
+
+// Exclusive prefix of queue q for `chunk`: wave 0 reads the status words of
+// the 64 preceding chunks at once, finds the nearest inclusive prefix by
+// ballot and adds the aggregates up to it; a window without an inclusive
+// prefix is summed whole and the window moves 64 chunks back.
+__device__ __forceinline__ uint32_t lookback_queue(const uint64_t* status, uint32_t chunk, uint32_t epoch, int q,
+                                                   uint32_t* err)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t excl = 0;
+    long long hi = (long long)chunk - 1;
+    uint32_t spins = 0;
+    while (hi >= 0) {
+        const long long j = hi - lane;
+        uint64_t s = pack_status(epoch, kFlagInc, 0);   // before chunk 0: an inclusive zero
+        if (j >= 0) s = __hip_atomic_load(status + (size_t)j * 3 + q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = (uint32_t)(s >> 34) == epoch && ((s >> 32) & 3ull) != 0;
+        const bool inc = ok && ((s >> 32) & 3ull) == kFlagInc;
+        const uint64_t inc_mask = __ballot(inc);
+        const uint64_t bad_mask = __ballot(!ok);
+        const int first_inc = inc_mask ? __ffsll((unsigned long long)inc_mask) - 1 : 64;
+        const uint64_t need = first_inc >= 63 ? ~0ull : ((2ull << first_inc) - 1ull);
+        if ((bad_mask & need) && ++spins < kMaxSpins) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        if (bad_mask & need) atomicOr(err, 2u);   // gave up waiting: missing values count as zero
+        spins = 0;
+        const uint32_t v = (((need >> lane) & 1ull) && ok) ? (uint32_t)s : 0u;
+        excl += wave_sum(v);
+        if (first_inc < 64) break;
+        hi -= 64;
+    }
+    return excl;
+}
+
 // Publish this chunk's aggregates, look back for the exclusive prefix of each
-// queue, publish the inclusive prefix.  Called by all threads; lanes 0..2 of
-// wave 0 do the work; the result lands in sh.prefix.
+// queue, publish the inclusive prefix.  Called by all threads; wave 0 does the
+// work; the result lands in sh.prefix / sh.total.
 template <int BLOCK>
 __device__ __forceinline__ void lookback3(uint64_t* status, uint32_t chunk, uint32_t epoch, const int tot[3],
-                                          ScanShared<BLOCK>& sh)
+                                          ScanShared<BLOCK>& sh, uint32_t* err)
 {
-    const int q = threadIdx.x;
-    if (q < 3) {
-        uint64_t* my = status + (size_t)chunk * 3 + q;
-        uint32_t excl = 0;
-        if (chunk == 0) {
-            __hip_atomic_store(my, pack_status(epoch, kFlagInc, (uint32_t)tot[q]), __ATOMIC_RELEASE,
+    if (threadIdx.x < 64) {
+        const int q = threadIdx.x;
+        // this lane's queue total, selected without indexing a register array
+        const uint32_t mine = (uint32_t)(q == 0 ? tot[0] : (q == 1 ? tot[1] : tot[2]));
+        if (q < 3)
+            __hip_atomic_store(status + (size_t)chunk * 3 + q,
+                               pack_status(epoch, chunk == 0 ? kFlagInc : kFlagAgg, mine), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(my, pack_status(epoch, kFlagAgg, (uint32_t)tot[q]), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            long long j = (long long)chunk - 1;
-            while (j >= 0) {
-                const uint64_t s = __hip_atomic_load(status + (size_t)j * 3 + q, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t ep = (uint32_t)(s >> 34);
-                const uint64_t fl = (s >> 32) & 3ull;
-                if (ep != epoch || fl == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += (uint32_t)s;
-                if (fl == kFlagInc) break;
-                --j;
-            }
-            __hip_atomic_store(my, pack_status(epoch, kFlagInc, excl + (uint32_t)tot[q]), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t e0 = 0, e1 = 0, e2 = 0;
+        if (chunk > 0) {
+            e0 = lookback_queue(status, chunk, epoch, 0, err);
+            e1 = lookback_queue(status, chunk, epoch, 1, err);
+            e2 = lookback_queue(status, chunk, epoch, 2, err);
         }
-        sh.prefix[q] = (int)excl;
-        sh.total[q] = tot[q];
+        const uint32_t ex = q == 0 ? e0 : (q == 1 ? e1 : e2);
+        if (q < 3) {
+            if (chunk > 0)
+                __hip_atomic_store(status + (size_t)chunk * 3 + q, pack_status(epoch, kFlagInc, ex + mine),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            sh.prefix[q] = (int)ex;
+            sh.total[q] = (int)mine;
+        }
     }
     __syncthreads();
 }

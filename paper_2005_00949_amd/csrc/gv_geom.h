@@ -87,23 +87,23 @@ __device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], cons
 #pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[v - 1]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[v]};
-    double best = kInf;
+    double best = kInf, plane = hi[2];
     int face = 5;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] < 0.0) {
             const double t = (lo[a] - p[a]) / d[a];
-            if (t < best) { best = t; face = 2 * a; }
+            if (t < best) { best = t; face = 2 * a; plane = lo[a]; }
         } else if (d[a] > 0.0) {
             const double t = (hi[a] - p[a]) / d[a];
-            if (t < best) { best = t; face = 2 * a + 1; }
+            if (t < best) { best = t; face = 2 * a + 1; plane = hi[a]; }
         }
     }
     Hit h;
     h.t = best > 0.0 ? best : 0.0;
     h.next = face == 4 ? (v == 1 ? 0 : v - 1) : face == 5 ? (v == g.n_vol ? 0 : v + 1) : 0;
     h.snap_axis = face >> 1;
-    h.snap_val = (face & 1) ? hi[face >> 1] : lo[face >> 1];
+    h.snap_val = plane;
     return h;
 }
 
@@ -121,7 +121,7 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
 #pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
-    double tn = -kInf, tf = kInf;
+    double tn = -kInf, tf = kInf, plane = 0.0;
     int an = -1;
     bool miss = false;
 #pragma unroll
@@ -131,7 +131,7 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
         } else {
             const double t1 = (lo[a] - p[a]) / d[a], t2 = (hi[a] - p[a]) / d[a];
             const double tmin = fmin(t1, t2), tmax = fmax(t1, t2);
-            if (tmin > tn) { tn = tmin; an = a; }
+            if (tmin > tn) { tn = tmin; an = a; plane = d[a] > 0.0 ? lo[a] : hi[a]; }
             if (tmax < tf) tf = tmax;
         }
     }
@@ -144,7 +144,7 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
         if (tn > 0.0) {
             h.t = tn;
             h.snap_axis = an;
-            h.snap_val = d[an] > 0.0 ? lo[an] : hi[an];
+            h.snap_val = plane;
             h.next = an == 2 ? (d[2] > 0.0 ? 1 : g.n_vol) : stack_of(g, p[2] + tn * d[2]);
         } else {
             h.t = 0.0;

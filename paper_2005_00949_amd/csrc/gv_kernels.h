@@ -139,7 +139,8 @@ __device__ __forceinline__ void account_rare(const Sinks& S, uint32_t ev, const 
     }
     if (o.proc >= 0) atomicAdd(&lds_cnt[kCProc + o.proc], 1u);
     if (o.rej_exhausted) atomicAdd(&lds_cnt[kCRej], (unsigned)o.rej_exhausted);
-    for (int c = 0; c < o.nchild; ++c) atomicAdd(&lds_cnt[kCTracks + o.ch[c].type], 1u);
+    if (o.nchild > 0) atomicAdd(&lds_cnt[kCTracks + o.ch[0].type], 1u);
+    if (o.nchild > 1) atomicAdd(&lds_cnt[kCTracks + o.ch[1].type], 1u);
 }
 
 __device__ __forceinline__ void deposit(const Sinks& S, uint32_t ev, int vol, double e)
@@ -377,6 +378,7 @@ __global__ void __launch_bounds__(BLOCK) k_dbg_compact(const int8_t* codes, long
                                                        uint32_t* counts, uint32_t* ticket, uint64_t* status,
                                                        uint32_t epoch)
 {
+    uint32_t* err = counts + 3;
     __shared__ ScanShared<BLOCK> sh;
     const long long n_chunks = (n + BLOCK - 1) / BLOCK;
     for (;;) {
@@ -394,7 +396,7 @@ __global__ void __launch_bounds__(BLOCK) k_dbg_compact(const int8_t* codes, long
             if (code[j] >= 0) cnt[code[j]]++;
         int excl[3], tot[3];
         block_scan3<BLOCK>(cnt, excl, tot, sh);
-        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh);
+        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh, err);
         int local[3] = {0, 0, 0};
         for (int j = 0; j < 3; ++j) {
             const int q = code[j];
@@ -415,13 +417,14 @@ struct Ctrl {
     uint32_t count[2][4];   // queue sizes by buffer parity and type
     uint32_t ticket;        // next basket to claim
     uint32_t epoch;         // launch counter tagging look-back status words
-    uint32_t overflow;      // a queue ran out of capacity
+    uint32_t overflow;      // bit 0: a queue ran out of capacity; bit 1: a look-back wait gave up
     uint32_t done;          // workgroups finished in this launch
     uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
 };
 
 template <class P> struct BatchArgs {
-    Soa<P> q[2][3];          // [parity][type]
+    Soa<P> in[3];            // input queues of this launch, by type
+    Soa<P> out[3];           // output queues, by type
     Ctrl* ctrl;
     uint64_t* status;
     uint32_t cap;
@@ -469,17 +472,19 @@ __global__ void k_ingest(const PrimDev* prim, long long n, const uint32_t* slot,
     if (q.type) q.type[k] = (int8_t)p.type;
 }
 
-// end of a launch, run by the last workgroup to finish: the consumed input
-// counts become the next launch's (empty) output, the basket ticket restarts
-// and the look-back epoch advances.  Every workgroup has read the control
-// block before it increments `done`, so nothing reads these words afterwards.
-__device__ __forceinline__ void finish_launch(Ctrl* ctrl, int parity)
+// end of a launch, run by the last of the `participants` workgroups to
+// finish: the consumed input counts become the next launch's (empty) output,
+// the basket ticket restarts and the look-back epoch advances.  Every
+// participant has read the control block before it increments `done`, and
+// the other workgroups left without touching it, so nothing reads these words
+// afterwards.
+__device__ __forceinline__ void finish_launch(Ctrl* ctrl, int parity, uint32_t participants)
 {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t d = atomicAdd(&ctrl->done, 1u);
-        if (d == gridDim.x - 1) {
+        if (d == participants - 1) {
             __threadfence();
             ctrl->count[parity][0] = 0;
             ctrl->count[parity][1] = 0;
@@ -492,24 +497,127 @@ __device__ __forceinline__ void finish_launch(Ctrl* ctrl, int parity)
     }
 }
 
+// write a secondary into the output queue of its type
+template <class P, class R = typename P::R>
+__device__ __forceinline__ void store_child_q(const BatchArgs<P>& A, int q, uint32_t pos, const Track<P>& parent,
+                                              const Child<R>& ch)
+{
+    if (q == kGamma) store_child(A.out[kGamma], pos, parent, ch);
+    else if (q == kElectron) store_child(A.out[kElectron], pos, parent, ch);
+    else store_child(A.out[kPositron], pos, parent, ch);
+}
+
+template <int Q> __device__ __forceinline__ int is_q(int t) { return t == Q ? 1 : 0; }
+__device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[0] : (q == 1 ? v[1] : v[2]); }
+
+// One chunk of BLOCK same-type tracks (TY known at compile time, so the
+// photon and charged-particle step paths are specialised): step each track up
+// to `inner` times in registers, stopping at its first secondary or its end;
+// then compact survivor + secondaries into the output queues.
+template <class P, int TY, int BLOCK, class R = typename P::R>
+__device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
+                                              uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
+                                              unsigned* cnt_lds, uint32_t& steps_here, uint32_t& loads,
+                                              uint32_t& stores, uint32_t n_chunks)
+{
+    const uint32_t slot = base + threadIdx.x;
+    const bool active = slot < n_t;
+    Track<P> t;
+    StepOut<R> o;
+    o.status = kDead;
+    o.nchild = 0;
+    o.ch[0].type = -1;
+    o.ch[1].type = -1;
+    if (active) {
+        load_track(A.in[TY], slot, TY, t);
+        t.type = TY;
+        loads += 1;
+        double acc = 0.0;
+        int acc_vol = t.vol;
+        for (int k = 0; k < inner; ++k) {
+            const uint32_t ns = t.nstep;
+            step_track(c, t, o);
+            steps_here += o.did_step;
+            if (o.vol_pre != acc_vol) {
+                deposit(A.S, t.ev, acc_vol, acc);
+                acc = 0.0;
+                acc_vol = o.vol_pre;
+            }
+            acc += o.edep;
+            if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
+            account_rare(A.S, t.ev, o, cnt_lds);
+            if (o.status != kAlive || o.nchild > 0) break;
+        }
+        deposit(A.S, t.ev, acc_vol, acc);
+    }
+    const int alive = (active && o.status == kAlive) ? 1 : 0;
+    const int q1 = o.nchild > 0 ? o.ch[0].type : -1;
+    const int q2 = o.nchild > 1 ? o.ch[1].type : -1;
+    int cnt[3];
+    cnt[0] = (TY == 0 ? alive : 0) + is_q<0>(q1) + is_q<0>(q2);
+    cnt[1] = (TY == 1 ? alive : 0) + is_q<1>(q1) + is_q<1>(q2);
+    cnt[2] = (TY == 2 ? alive : 0) + is_q<2>(q1) + is_q<2>(q2);
+    int excl[3], tot[3];
+    block_scan3<BLOCK>(cnt, excl, tot, sh);
+    lookback3<BLOCK>(A.status, chunk, epoch, tot, sh, &A.ctrl->overflow);
+    // output positions in expanded order: survivor, child 0, child 1
+    if (alive) {
+        const uint32_t pos = (uint32_t)sh.prefix[TY] + (uint32_t)excl[TY];
+        if (pos < A.cap) {
+            store_track(A.out[TY], pos, t);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    if (q1 >= 0) {
+        const uint32_t pos = (uint32_t)sh.prefix[q1] + (uint32_t)pick3(q1, excl) + (uint32_t)((q1 == TY) & alive);
+        if (pos < A.cap) {
+            store_child_q(A, q1, pos, t, o.ch[0]);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    if (q2 >= 0) {
+        const uint32_t pos = (uint32_t)sh.prefix[q2] + (uint32_t)pick3(q2, excl) +
+                             (uint32_t)((q2 == TY) & alive) + (uint32_t)(q2 == q1);
+        if (pos < A.cap) {
+            store_child_q(A, q2, pos, t, o.ch[1]);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    if (chunk == n_chunks - 1 && threadIdx.x < 3) {
+        const uint32_t total = (uint32_t)(sh.prefix[threadIdx.x] + sh.total[threadIdx.x]);
+        A.ctrl->count[A.parity ^ 1][threadIdx.x] = total < A.cap ? total : A.cap;
+    }
+    __syncthreads();
+}
+
 template <class P, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
 {
-    using R = typename P::R;
     __shared__ ScanShared<BLOCK> sh;
     __shared__ unsigned cnt_lds[kNCount];
     for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
 
-    const int pin = A.parity, pout = A.parity ^ 1;
+    const int pin = A.parity;
     const uint32_t n0 = A.ctrl->count[pin][0], n1 = A.ctrl->count[pin][1], n2 = A.ctrl->count[pin][2];
     const uint32_t epoch = A.ctrl->epoch;
     const uint32_t c0 = (n0 + BLOCK - 1) / BLOCK, c1 = (n1 + BLOCK - 1) / BLOCK, c2 = (n2 + BLOCK - 1) / BLOCK;
     const uint32_t n_chunks = c0 + c1 + c2;
     const uint32_t population = n0 + n1 + n2;
     const int inner = population < A.tail_threshold ? A.inner_tail : A.inner_bulk;
+    // only as many workgroups as there are baskets take part; the rest leave
+    // at once, so a small population costs a small launch
+    const uint32_t baskets = (n_chunks + (uint32_t)A.basket_chunks - 1) / (uint32_t)A.basket_chunks;
+    const uint32_t participants = baskets < gridDim.x ? (baskets > 0 ? baskets : 1u) : gridDim.x;
+    if (blockIdx.x >= participants) return;
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
-    uint32_t steps_here[3] = {0, 0, 0};
-    uint32_t loads_here = 0, stores_here = 0;
+    uint32_t steps_g = 0, steps_e = 0, steps_p = 0;
+    uint32_t loads = 0, stores = 0;
     __syncthreads();
 
     for (;;) {
@@ -520,80 +628,26 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
         if (first >= n_chunks) break;
         const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
         for (uint32_t chunk = first; chunk < last; ++chunk) {
-            int type;
-            uint32_t base, n_t;
-            if (chunk < c0) { type = kGamma; base = chunk * BLOCK; n_t = n0; }
-            else if (chunk < c0 + c1) { type = kElectron; base = (chunk - c0) * BLOCK; n_t = n1; }
-            else { type = kPositron; base = (chunk - c0 - c1) * BLOCK; n_t = n2; }
-            const uint32_t slot = base + threadIdx.x;
-            const bool active = slot < n_t;
-            Track<P> t;
-            StepOut<R> o;
-            o.status = kDead;
-            o.nchild = 0;
-            if (active) {
-                load_track(A.q[pin][type], slot, type, t);
-                loads_here += 1;
-                double acc = 0.0;
-                int acc_vol = t.vol;
-                for (int k = 0; k < inner; ++k) {
-                    const uint32_t ns = t.nstep;
-                    step_track(c, t, o);
-                    if (o.did_step) steps_here[type] += 1;
-                    if (o.vol_pre != acc_vol) {
-                        deposit(A.S, t.ev, acc_vol, acc);
-                        acc = 0.0;
-                        acc_vol = o.vol_pre;
-                    }
-                    acc += o.edep;
-                    if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
-                    account_rare(A.S, t.ev, o, cnt_lds);
-                    if (o.status != kAlive || o.nchild > 0) break;
-                }
-                deposit(A.S, t.ev, acc_vol, acc);
-            }
-            // outputs: survivor then children, each to the queue of its type
-            int code[3] = {-1, -1, -1};
-            if (active) {
-                if (o.status == kAlive) code[0] = type;
-                for (int k = 0; k < o.nchild; ++k) code[1 + k] = o.ch[k].type;
-            }
-            int cnt[3] = {0, 0, 0};
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                if (code[j] >= 0) cnt[code[j]]++;
-            int excl[3], tot[3];
-            block_scan3<BLOCK>(cnt, excl, tot, sh);
-            lookback3<BLOCK>(A.status, chunk, epoch, tot, sh);
-            int local[3] = {0, 0, 0};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int q = code[j];
-                if (q < 0) continue;
-                const uint32_t pos = (uint32_t)sh.prefix[q] + (uint32_t)excl[q] + (uint32_t)local[q]++;
-                if (pos >= A.cap) {
-                    A.ctrl->overflow = 1u;
-                    continue;
-                }
-                if (j == 0) store_track(A.q[pout][q], pos, t);
-                else store_child(A.q[pout][q], pos, t, o.ch[j - 1]);
-                stores_here += 1;
-            }
-            if (chunk == n_chunks - 1 && threadIdx.x < 3) {
-                const uint32_t total = (uint32_t)(sh.prefix[threadIdx.x] + sh.total[threadIdx.x]);
-                A.ctrl->count[pout][threadIdx.x] = total < A.cap ? total : A.cap;
-            }
-            __syncthreads();
+            if (chunk < c0)
+                process_chunk<P, kGamma, BLOCK>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, cnt_lds, steps_g,
+                                                loads, stores, n_chunks);
+            else if (chunk < c0 + c1)
+                process_chunk<P, kElectron, BLOCK>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, cnt_lds,
+                                                   steps_e, loads, stores, n_chunks);
+            else
+                process_chunk<P, kPositron, BLOCK>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh,
+                                                   cnt_lds, steps_p, loads, stores, n_chunks);
         }
     }
-    // flush counters
-    for (int ty = 0; ty < 3; ++ty) atomicAdd(&cnt_lds[kCSteps + ty], steps_here[ty]);
-    atomicAdd(&cnt_lds[kCLoads], loads_here);
-    atomicAdd(&cnt_lds[kCStores], stores_here);
+    atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);
+    atomicAdd(&cnt_lds[kCSteps + kElectron], steps_e);
+    atomicAdd(&cnt_lds[kCSteps + kPositron], steps_p);
+    atomicAdd(&cnt_lds[kCLoads], loads);
+    atomicAdd(&cnt_lds[kCStores], stores);
     __syncthreads();
     for (int i = threadIdx.x; i < kNCount; i += BLOCK)
         if (cnt_lds[i]) atomicAdd(&A.S.counters[i], (unsigned long long)cnt_lds[i]);
-    finish_launch(A.ctrl, pin);
+    finish_launch(A.ctrl, pin, participants);
 }
 
 // ===========================================================================
@@ -739,6 +793,9 @@ __global__ void __launch_bounds__(BLOCK) k_plain_compact(PlainArgs A, Soa<P64> n
 {
     __shared__ ScanShared<BLOCK> sh;
     const long long n_chunks = (A.n + BLOCK - 1) / BLOCK;
+    const uint32_t participants = n_chunks < (long long)gridDim.x ? (uint32_t)(n_chunks > 0 ? n_chunks : 1)
+                                                                  : gridDim.x;
+    if (blockIdx.x >= participants) return;
     const uint32_t epoch = ctrl->epoch;
     uint32_t* count_out = &ctrl->count[parity ^ 1][0];
     uint32_t* overflow = &ctrl->overflow;
@@ -762,17 +819,17 @@ __global__ void __launch_bounds__(BLOCK) k_plain_compact(PlainArgs A, Soa<P64> n
         }
         int excl[3], tot[3];
         block_scan3<BLOCK>(cnt, excl, tot, sh);
-        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh);
+        lookback3<BLOCK>(status, (uint32_t)chunk, epoch, tot, sh, overflow);
         uint32_t pos = (uint32_t)sh.prefix[0] + (uint32_t)excl[0];
         if (i < A.n) {
             if (o.status == kAlive) {
                 if (pos < cap) store_track(next, pos, t);
-                else *overflow = 1u;
+                else atomicOr(overflow, 1u);
                 ++pos;
             }
             for (int k = 0; k < o.nchild; ++k, ++pos) {
                 if (pos < cap) store_child(next, pos, t, o.ch[k]);
-                else *overflow = 1u;
+                else atomicOr(overflow, 1u);
             }
         }
         if (chunk == n_chunks - 1 && threadIdx.x == 0) {
@@ -781,7 +838,7 @@ __global__ void __launch_bounds__(BLOCK) k_plain_compact(PlainArgs A, Soa<P64> n
         }
         __syncthreads();
     }
-    finish_launch(ctrl, parity);
+    finish_launch(ctrl, parity, participants);
 }
 
 }  // namespace gv

@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -166,8 +167,10 @@ struct Lib {
     DBuf<PrimDev> prim;
     DBuf<uint32_t> prim_slot;
     Ctrl* h_ctrl = nullptr;  // pinned
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec = nullptr;      // bulk: full grid, bulk inner steps
     hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec_tail = nullptr; // tail: small grid, tail inner steps
+    hipGraph_t graph_tail = nullptr;
     GraphKey gkey;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     gv_stats_t stats{};
@@ -175,6 +178,7 @@ struct Lib {
     int64_t last_events = 0;
     double init_ms = 0.0;
     double plain_loads = 0.0, plain_stores = 0.0;
+    bool progress = std::getenv("GV_PROGRESS") != nullptr;   // print the population per graph replay
     // the staged batch (gv_stage): primaries grouped by event, resident on the device
     std::vector<PrimDev> hp;
     std::vector<size_t> ev_start;
@@ -217,8 +221,12 @@ void drop_graph()
 {
     if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
     if (L.graph) (void)hipGraphDestroy(L.graph);
+    if (L.gexec_tail) (void)hipGraphExecDestroy(L.gexec_tail);
+    if (L.graph_tail) (void)hipGraphDestroy(L.graph_tail);
     L.gexec = nullptr;
     L.graph = nullptr;
+    L.gexec_tail = nullptr;
+    L.graph_tail = nullptr;
     L.gkey = GraphKey{};
 }
 
@@ -400,7 +408,9 @@ int apply_run_params()
 
 struct Tuning {
     int block, chunks, occupancy, inner_bulk, inner_tail, K;
-    uint32_t tail;
+    uint32_t tail;       // population below which the tail graph runs
+    int tail_grid;       // workgroups of a tail launch
+    int tail_K;          // launches per tail graph replay
 };
 
 Tuning pick_tuning(int n_primaries)
@@ -414,6 +424,8 @@ Tuning pick_tuning(int n_primaries)
     t.inner_tail = std::max(t.inner_bulk, 256);
     t.K = L.cfg.graph_steps ? L.cfg.graph_steps : 16;
     t.tail = (uint32_t)std::min<long long>((long long)L.n_cu * t.block * 2, 1u << 30);
+    t.tail_grid = t.occupancy * L.n_cu;
+    t.tail_K = 4 * t.K;
     (void)n_primaries;
     return t;
 }
@@ -555,32 +567,44 @@ template <class P> QueueMem<P>& batch_queues();
 template <> QueueMem<P64>& batch_queues<P64>() { return L.q64; }
 template <> QueueMem<PMix>& batch_queues<PMix>() { return L.qmix; }
 
-template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
+// capture K launches alternating parity (K even: a replay ends where it began)
+template <class P>
+int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, hipGraph_t* g, hipGraphExec_t* ge)
 {
-    drop_graph();
     QueueMem<P>& Q = batch_queues<P>();
     hipStream_t s = stream();
     BatchArgs<P> A[2];
     for (int par = 0; par < 2; ++par) {
-        for (int p = 0; p < 2; ++p)
-            for (int t = 0; t < 3; ++t) A[par].q[p][t] = Q.q[p][t];
+        for (int t = 0; t < 3; ++t) {
+            A[par].in[t] = Q.q[par][t];
+            A[par].out[t] = Q.q[par ^ 1][t];
+        }
         A[par].ctrl = L.ctrl.p;
         A[par].status = L.status.p;
         A[par].cap = (uint32_t)Q.cap;
         A[par].parity = par;
         A[par].basket_chunks = tu.chunks;
-        A[par].inner_bulk = tu.inner_bulk;
-        A[par].inner_tail = tu.inner_tail;
+        A[par].inner_bulk = inner_bulk;
+        A[par].inner_tail = inner_tail;
         A[par].tail_threshold = tu.tail;
         A[par].S = make_sinks();
         A[par].tv = tab_view<typename P::R>();
     }
-    const int grid = tu.occupancy * L.n_cu;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < tu.K; ++k) launch_step_dispatch<P>(tu.block, A[k & 1], grid, s);
-    hipError_t ce = hipStreamEndCapture(s, &L.graph);
+    for (int k = 0; k < K; ++k) launch_step_dispatch<P>(tu.block, A[k & 1], grid, s);
+    hipError_t ce = hipStreamEndCapture(s, g);
     if (ce != hipSuccess) return fail(GV_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
-    HIPCHK(hipGraphInstantiate(&L.gexec, L.graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphInstantiate(ge, *g, nullptr, nullptr, 0));
+    return GV_OK;
+}
+
+template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
+{
+    drop_graph();
+    int rc = capture<P>(tu, tu.occupancy * L.n_cu, tu.K, tu.inner_bulk, tu.inner_tail, &L.graph, &L.gexec);
+    if (rc) return rc;
+    rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, &L.graph_tail, &L.gexec_tail);
+    if (rc) return rc;
     L.gkey = key;
     return GV_OK;
 }
@@ -612,21 +636,33 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
         if (rc) return rc;
     }
     hipStream_t s = stream();
+    uint32_t population = counts[0] + counts[1] + counts[2];
+    uint32_t peak = population;
     for (;;) {
+        // once the population has passed its peak and fallen below the tail
+        // threshold, replay the tail graph (more launches per replay)
+        const bool tail = population < tu.tail && peak >= tu.tail;
         HIPCHK(hipEventRecord(L.ev0, s));
-        HIPCHK(hipGraphLaunch(L.gexec, s));
+        HIPCHK(hipGraphLaunch(tail ? L.gexec_tail : L.gexec, s));
         HIPCHK(hipEventRecord(L.ev1, s));
         rc = read_ctrl();
         if (rc) return rc;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, L.ev0, L.ev1));
+        const int K = tail ? tu.tail_K : tu.K;
         L.stats.kernel_ms += ms;
-        L.stats.kernel_launches += tu.K;
-        L.stats.iterations += tu.K;
+        L.stats.kernel_launches += K;
+        L.stats.iterations += K;
         L.stats.graph_replays += 1;
+        if (L.h_ctrl->overflow & 2u) return fail(GV_E_STATE, "compaction look-back wait exceeded its bound");
         if (L.h_ctrl->overflow) return GV_E_CAPACITY;
         const uint32_t* c = L.h_ctrl->count[0];
-        if (c[0] + c[1] + c[2] == 0) break;
+        if (L.progress)
+            std::fprintf(stderr, "[gv] replay %lld %s: %.3f ms, population %u/%u/%u\n",
+                         (long long)L.stats.graph_replays, tail ? "tail" : "bulk", ms, c[0], c[1], c[2]);
+        population = c[0] + c[1] + c[2];
+        peak = std::max(peak, population);
+        if (population == 0) break;
         // every launch advances each live track by at least one step, so the
         // looper cap bounds the number of launches
         if (L.stats.iterations > 2 * L.cfg.max_steps_per_track + 64)
@@ -685,6 +721,7 @@ int run_plain_window(size_t b, size_t e, uint64_t seed)
         L.stats.kernel_ms += ms;
         L.stats.kernel_launches += 7;
         L.stats.iterations += 1;
+        if (L.h_ctrl->overflow & 2u) return fail(GV_E_STATE, "compaction look-back wait exceeded its bound");
         if (L.h_ctrl->overflow) return GV_E_CAPACITY;
         L.plain_loads += n;
         parity ^= 1;
@@ -1212,6 +1249,7 @@ int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
         HIPCHK(hipMemcpyAsync(io->index, dq, sizeof(int) * 9 * n, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hc, dcnt, 16, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (hc[3] & 2u) return fail(GV_E_STATE, "compaction look-back wait exceeded its bound");
         for (int q = 0; q < 3; ++q) io->counts[q] = hc[q];
         return GV_OK;
     }

@@ -119,15 +119,22 @@ __device__ __forceinline__ void child_ids(const Ctx<P>& c, const Track<P>& t, ui
     ids[1] = ((uint64_t)b.w[3] << 32) | b.w[2];
 }
 
-template <class R> __device__ __forceinline__ void add_child(StepOut<R>& o, int type, R T, const R u[3], uint64_t tid)
+template <class R> __device__ __forceinline__ void set_child(Child<R>& ch, int type, R T, const R u[3], uint64_t tid)
 {
-    Child<R>& ch = o.ch[o.nchild++];
     ch.type = type;
     ch.T = T;
     ch.u[0] = u[0];
     ch.u[1] = u[1];
     ch.u[2] = u[2];
     ch.tid = tid;
+}
+
+// append a secondary (constant-index stores keep the record in registers)
+template <class R> __device__ __forceinline__ void add_child(StepOut<R>& o, int type, R T, const R u[3], uint64_t tid)
+{
+    if (o.nchild == 0) set_child(o.ch[0], type, T, u, tid);
+    else set_child(o.ch[1], type, T, u, tid);
+    o.nchild += 1;
 }
 
 // e+ at rest: two back-to-back 511 keV photons, isotropic (ANNIH block)
@@ -233,7 +240,9 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
 #pragma unroll
         for (int a = 0; a < 3; ++a) t.x[a] += pr.s * (double)t.u[a];
         if (pr.lim == kLimGeom) {
-            if (G.snap_axis >= 0) t.x[G.snap_axis] = G.snap_val;
+            if (G.snap_axis == 0) t.x[0] = G.snap_val;
+            else if (G.snap_axis == 1) t.x[1] = G.snap_val;
+            else if (G.snap_axis == 2) t.x[2] = G.snap_val;
             t.vol = G.next;
             pr.crossed = 1;
         }
