@@ -161,6 +161,20 @@ def run_cpu_baseline(args):
                 primaries_per_s=len(sample) / dt)
 
 
+def copy_probe(nbytes, reps):
+    """Device-to-device copy of a known size: the calibration run for the HBM
+    byte counters (their reading for this copy against 2 x nbytes moved)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: {reps} x {n * 4} bytes read and written")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,7 +190,12 @@ def main():
     ap.add_argument("--cpu-events", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 3)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); events shard "
               f"across GPUs without communication, see the design notes", file=sys.stderr)

@@ -48,6 +48,14 @@ enum { GV_AXIS_Z_SLABS = 0, GV_AXIS_R_SHELLS = 1 };
 enum { GV_DRIVER_PLAIN = 0, GV_DRIVER_BATCHED = 1 };
 enum { GV_P64 = 0, GV_PMIX = 1 };
 enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1 };
+/* Order of tracks in the batched driver's queues between step launches.
+ * ARRIVAL: each basket reserves its output range when it finishes (one
+ * atomic add per queue), so queue order across baskets follows completion
+ * order; within a basket it is slot order.  STABLE: output order is the
+ * order of the input slots (single-pass look-back over the claimed baskets),
+ * identical in every run.  Results are the same in both: a track's random
+ * numbers are keyed by (event, track id, step), never by its queue slot. */
+enum { GV_ORDER_ARRIVAL = 0, GV_ORDER_STABLE = 1 };
 
 /* A material: density and elemental composition by mass fraction.  The
  * library derives electron density, radiation length (Tsai, unless X0_cm > 0),
@@ -129,6 +137,8 @@ typedef struct {
     double rk_frac;                 /* RK4 substep as a fraction of the radius, default 0.05 */
     void* hip_stream;               /* hipStream_t to run on; NULL = the library's own */
     int64_t trace_cap;              /* > 0: record up to this many step records (tests) */
+    int32_t queue_order;            /* GV_ORDER_ARRIVAL (default) or GV_ORDER_STABLE; batched driver */
+    int32_t reserved;               /* must be 0 */
 } gv_config;
 
 /* Counters of the last gv_transport. */

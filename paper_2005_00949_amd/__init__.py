@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "GV_OK", 1: "GV_E_INVALID_ARG", 2: "GV_E_GEOMETRY", 3: "GV_E_
 DRIVER_PLAIN, DRIVER_BATCHED = 0, 1
 P64, PMIX = 0, 1
 FIELD_HELIX, FIELD_RK4 = 0, 1
+ORDER_ARRIVAL, ORDER_STABLE = 0, 1
 DBG_STEP, DBG_PHILOX, DBG_COMPACT, DBG_TABLE, DBG_GEOM = 0, 1, 2, 3, 4
 MAX_ELEM = 8
 PROC_NAMES = ["compton", "pair", "moller", "bhabha", "brems_em", "brems_ep", "annihilation", "null"]
@@ -58,7 +59,7 @@ class Config(C.Structure):
                 ("max_steps_per_track", C.c_int64), ("capacity", C.c_int64),
                 ("max_events_in_flight", C.c_int64), ("chord_tol_cm", C.c_double),
                 ("push_cm", C.c_double), ("rk_frac", C.c_double), ("hip_stream", C.c_void_p),
-                ("trace_cap", C.c_int64)]
+                ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -175,7 +176,8 @@ class Engine:
         self.config = dict(driver=DRIVER_BATCHED, precision=PMIX, basket=0, occupancy=0, inner_steps=0,
                            graph_steps=0, field_method=FIELD_HELIX, edep_on_device=0,
                            max_steps_per_track=1 << 20, capacity=0, max_events_in_flight=0,
-                           chord_tol_cm=1e-3, push_cm=1e-7, rk_frac=0.05, hip_stream=None, trace_cap=0)
+                           chord_tol_cm=1e-3, push_cm=1e-7, rk_frac=0.05, hip_stream=None, trace_cap=0,
+                           queue_order=ORDER_ARRIVAL)
         self.configure(**config)
 
     def configure(self, **kw):

@@ -1,6 +1,7 @@
-// gv_compact.h -- stable three-way compaction of track outputs into the
+// gv_compact.h -- three-way compaction of track outputs into the
 // per-particle-type queues (the stage baskets and survivor stack of
-// Sec. 2.1.1-2.1.2, realised as queues in HBM).
+// Sec. 2.1.1-2.1.2, realised as queues in HBM): stable across the whole
+// launch (look-back) or stable within each block (arrival-order reservation).
 //
 // Every input slot expands to at most three outputs (the surviving track and
 // two secondaries), each bound for one of three queues.  Output order in a
@@ -136,6 +137,29 @@ __device__ __forceinline__ void lookback3(uint64_t* status, uint32_t chunk, uint
             sh.prefix[q] = (int)ex;
             sh.total[q] = (int)mine;
         }
+    }
+    __syncthreads();
+}
+
+// Arrival-order placement: the block reserves its output range in each queue
+// with one atomic add on the queue's counter; the queue ends up holding the
+// blocks' outputs in the order the reservations landed, each block's outputs
+// in slot order.  No block waits for another.  A reservation that runs past
+// `cap` sets bit 0 of *err (stores beyond cap are skipped by the caller).
+template <int BLOCK>
+__device__ __forceinline__ void reserve3(uint32_t* count_out, uint32_t cap, const int tot[3], ScanShared<BLOCK>& sh,
+                                         uint32_t* err)
+{
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        const uint32_t mine = (uint32_t)(q == 0 ? tot[0] : (q == 1 ? tot[1] : tot[2]));
+        uint32_t base = 0;
+        if (mine) {
+            base = atomicAdd(count_out + q, mine);
+            if ((uint64_t)base + mine > cap) atomicOr(err, 1u);
+        }
+        sh.prefix[q] = (int)base;
+        sh.total[q] = (int)mine;
     }
     __syncthreads();
 }

@@ -419,6 +419,8 @@ struct Ctrl {
     uint32_t epoch;         // launch counter tagging look-back status words
     uint32_t overflow;      // bit 0: a queue ran out of capacity; bit 1: a look-back wait gave up
     uint32_t done;          // workgroups finished in this launch
+    uint32_t halt;          // overflow as seen at the end of the previous launch
+    uint32_t pad;
     uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
 };
 
@@ -491,6 +493,7 @@ __device__ __forceinline__ void finish_launch(Ctrl* ctrl, int parity, uint32_t p
             ctrl->count[parity][2] = 0;
             ctrl->ticket = 0;
             ctrl->done = 0;
+            ctrl->halt = ctrl->overflow;
             ctrl->epoch = ctrl->epoch + 1;
             __threadfence();
         }
@@ -514,7 +517,7 @@ __device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[
 // photon and charged-particle step paths are specialised): step each track up
 // to `inner` times in registers, stopping at its first secondary or its end;
 // then compact survivor + secondaries into the output queues.
-template <class P, int TY, int BLOCK, class R = typename P::R>
+template <class P, int TY, int BLOCK, bool STABLE, class R = typename P::R>
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               unsigned* cnt_lds, uint32_t& steps_here, uint32_t& loads,
@@ -559,7 +562,8 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
     cnt[2] = (TY == 2 ? alive : 0) + is_q<2>(q1) + is_q<2>(q2);
     int excl[3], tot[3];
     block_scan3<BLOCK>(cnt, excl, tot, sh);
-    lookback3<BLOCK>(A.status, chunk, epoch, tot, sh, &A.ctrl->overflow);
+    if (STABLE) lookback3<BLOCK>(A.status, chunk, epoch, tot, sh, &A.ctrl->overflow);
+    else reserve3<BLOCK>(&A.ctrl->count[A.parity ^ 1][0], A.cap, tot, sh, &A.ctrl->overflow);
     // output positions in expanded order: survivor, child 0, child 1
     if (alive) {
         const uint32_t pos = (uint32_t)sh.prefix[TY] + (uint32_t)excl[TY];
@@ -589,14 +593,14 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             atomicOr(&A.ctrl->overflow, 1u);
         }
     }
-    if (chunk == n_chunks - 1 && threadIdx.x < 3) {
+    if (STABLE && chunk == n_chunks - 1 && threadIdx.x < 3) {
         const uint32_t total = (uint32_t)(sh.prefix[threadIdx.x] + sh.total[threadIdx.x]);
         A.ctrl->count[A.parity ^ 1][threadIdx.x] = total < A.cap ? total : A.cap;
     }
     __syncthreads();
 }
 
-template <class P, int BLOCK>
+template <class P, int BLOCK, bool STABLE>
 __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
 {
     __shared__ ScanShared<BLOCK> sh;
@@ -604,7 +608,14 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
     for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
 
     const int pin = A.parity;
-    const uint32_t n0 = A.ctrl->count[pin][0], n1 = A.ctrl->count[pin][1], n2 = A.ctrl->count[pin][2];
+    // after an overflow (reported to the host, which reruns the window) the
+    // remaining launches of the replay do nothing; counts never exceed cap.
+    // `halt` changes only between launches, so every participant of this
+    // launch sees the same counts and the same participant number.
+    const bool ovf = A.ctrl->halt != 0;
+    const uint32_t n0 = ovf ? 0u : min(A.ctrl->count[pin][0], A.cap);
+    const uint32_t n1 = ovf ? 0u : min(A.ctrl->count[pin][1], A.cap);
+    const uint32_t n2 = ovf ? 0u : min(A.ctrl->count[pin][2], A.cap);
     const uint32_t epoch = A.ctrl->epoch;
     const uint32_t c0 = (n0 + BLOCK - 1) / BLOCK, c1 = (n1 + BLOCK - 1) / BLOCK, c2 = (n2 + BLOCK - 1) / BLOCK;
     const uint32_t n_chunks = c0 + c1 + c2;
@@ -629,13 +640,13 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
         const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
-                process_chunk<P, kGamma, BLOCK>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, cnt_lds, steps_g,
+                process_chunk<P, kGamma, BLOCK, STABLE>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, cnt_lds, steps_g,
                                                 loads, stores, n_chunks);
             else if (chunk < c0 + c1)
-                process_chunk<P, kElectron, BLOCK>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, cnt_lds,
+                process_chunk<P, kElectron, BLOCK, STABLE>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, cnt_lds,
                                                    steps_e, loads, stores, n_chunks);
             else
-                process_chunk<P, kPositron, BLOCK>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh,
+                process_chunk<P, kPositron, BLOCK, STABLE>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh,
                                                    cnt_lds, steps_p, loads, stores, n_chunks);
         }
     }

@@ -126,11 +126,12 @@ struct GraphKey {
     const void* edep = nullptr;
     const void* trace = nullptr;
     long long trace_cap = 0;
+    int order = -1;
     bool operator==(const GraphKey& o) const
     {
         return prec == o.prec && block == o.block && chunks == o.chunks && inner_bulk == o.inner_bulk &&
                inner_tail == o.inner_tail && K == o.K && tail == o.tail && cap == o.cap && qblock == o.qblock &&
-               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap;
+               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order;
     }
 };
 
@@ -212,6 +213,8 @@ gv_config default_config()
     c.rk_frac = 0.05;
     c.hip_stream = nullptr;
     c.trace_cap = 0;
+    c.queue_order = GV_ORDER_ARRIVAL;
+    c.reserved = 0;
     return c;
 }
 
@@ -389,6 +392,9 @@ int validate_config(const gv_config& c)
     if (!(c.chord_tol_cm > 0.0) || !(c.push_cm >= 0.0) || !(c.rk_frac > 0.0))
         return fail(GV_E_INVALID_ARG, "field tolerances");
     if (c.trace_cap < 0) return fail(GV_E_INVALID_ARG, "trace_cap");
+    if (c.queue_order != GV_ORDER_ARRIVAL && c.queue_order != GV_ORDER_STABLE)
+        return fail(GV_E_INVALID_ARG, "queue_order");
+    if (c.reserved != 0) return fail(GV_E_INVALID_ARG, "reserved field must be 0");
     return GV_OK;
 }
 
@@ -502,6 +508,7 @@ int upload_ctrl(const uint32_t counts[3], uint64_t seed)
     c.ticket = 0;
     c.overflow = 0;
     c.done = 0;
+    c.halt = 0;
     c.seed = seed;
     if (c.epoch == 0) c.epoch = 1;
     *L.h_ctrl = c;
@@ -549,17 +556,18 @@ int ingest(size_t b, size_t e, Soa<P> q[3], uint32_t counts[3], size_t cap, bool
     return GV_OK;
 }
 
-template <class P, int BLOCK> void launch_step(const BatchArgs<P>& A, int grid, hipStream_t s)
+template <class P, int BLOCK> void launch_step(const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
 {
-    k_step_batched<P, BLOCK><<<grid, BLOCK, 0, s>>>(A);
+    if (stable) k_step_batched<P, BLOCK, true><<<grid, BLOCK, 0, s>>>(A);
+    else k_step_batched<P, BLOCK, false><<<grid, BLOCK, 0, s>>>(A);
 }
 
-template <class P> void launch_step_dispatch(int block, const BatchArgs<P>& A, int grid, hipStream_t s)
+template <class P> void launch_step_dispatch(int block, const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
 {
     switch (block) {
-    case 64: launch_step<P, 64>(A, grid, s); break;
-    case 128: launch_step<P, 128>(A, grid, s); break;
-    default: launch_step<P, 256>(A, grid, s); break;
+    case 64: launch_step<P, 64>(A, grid, stable, s); break;
+    case 128: launch_step<P, 128>(A, grid, stable, s); break;
+    default: launch_step<P, 256>(A, grid, stable, s); break;
     }
 }
 
@@ -591,7 +599,8 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, h
         A[par].tv = tab_view<typename P::R>();
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < K; ++k) launch_step_dispatch<P>(tu.block, A[k & 1], grid, s);
+    const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
+    for (int k = 0; k < K; ++k) launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
     hipError_t ce = hipStreamEndCapture(s, g);
     if (ce != hipSuccess) return fail(GV_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
     HIPCHK(hipGraphInstantiate(ge, *g, nullptr, nullptr, 0));
@@ -631,6 +640,7 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     key.edep = L.edep.p;
     key.trace = L.cfg.trace_cap > 0 ? L.trace.p : nullptr;
     key.trace_cap = L.cfg.trace_cap;
+    key.order = L.cfg.queue_order;
     if (!L.gexec || !(L.gkey == key)) {
         rc = build_graph<P>(tu, key);
         if (rc) return rc;

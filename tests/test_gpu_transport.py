@@ -4,8 +4,10 @@
   FP64 GPU drivers equals the oracle's, with continuous fields within a
   history tolerance.
 * Per-event energy ledger closes for every driver and precision.
-* Determinism: identical histories for any basket / occupancy / inner-step
-  setting (deposits equal up to atomic summation order).
+* Determinism: identical histories for any basket / occupancy / inner-step /
+  queue-order setting (deposits equal up to atomic summation order).
+* Queue overflow: the event window is rerun with half the events in flight
+  and reproduces the unconstrained result.
 * Per-layer deposits of the mixed-precision batched path against the oracle:
   paired test, |mean difference| <= 3 sigma_paired and <= 0.5% for layers
   holding at least 1% of the deposit.
@@ -58,7 +60,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("driver", ["plain", "batched1", "batched8"])
+@pytest.mark.parametrize("driver", ["plain", "batched1", "batched8", "batched4_stable"])
 def test_tiny_shower_histories_fp64(gv, oracle_mod, case, driver):
     geom, prim = CASES[case][0](), CASES[case][1]()
     seed = 0x5EED
@@ -67,7 +69,8 @@ def test_tiny_shower_histories_fp64(gv, oracle_mod, case, driver):
     if driver == "plain":
         cfg["driver"] = gv.DRIVER_PLAIN
     else:
-        cfg.update(driver=gv.DRIVER_BATCHED, inner_steps=1 if driver == "batched1" else 8, basket=128)
+        cfg.update(driver=gv.DRIVER_BATCHED, inner_steps={"batched1": 1, "batched8": 8}.get(driver, 4), basket=128,
+                   queue_order=gv.ORDER_STABLE if driver.endswith("stable") else gv.ORDER_ARRIVAL)
     eng = gv.Engine(geom, **cfg)
     edep = eng.transport(prim, seed)
     got = eng.trace()
@@ -112,8 +115,8 @@ def test_ledger_closure(gv, name, n, mode):
 def test_determinism_across_knobs(gv):
     geom, prim, seed = gv_inputs.workload("c3", 20)
     ref = None
-    for basket, occ, inner in [(64, 1, 1), (512, 2, 4), (4096, 4, 16), (256, 8, 2)]:
-        eng = gv.Engine(geom, precision=gv.P64, basket=basket, occupancy=occ, inner_steps=inner)
+    for basket, occ, inner, order in [(64, 1, 1, 0), (512, 2, 4, 1), (4096, 4, 16, 0), (256, 8, 2, 1), (128, 2, 4, 0)]:
+        eng = gv.Engine(geom, precision=gv.P64, basket=basket, occupancy=occ, inner_steps=inner, queue_order=order)
         e = eng.transport(prim, seed)
         st = eng.stats()
         if ref is None:
@@ -121,6 +124,45 @@ def test_determinism_across_knobs(gv):
         else:
             assert st["total_steps"] == ref_steps
             assert np.allclose(e, ref, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["p64", "pmix"])
+def test_queue_orders_agree(gv, prec):
+    """Arrival-order and stable queues hold the same tracks in different
+    slots; keyed random streams make the physics identical: equal step,
+    track and interaction counts, deposits equal up to atomic summation order."""
+    geom, prim, seed = gv_inputs.workload("c4", 150)
+    p = gv.P64 if prec == "p64" else gv.PMIX
+    out = {}
+    for order in (gv.ORDER_STABLE, gv.ORDER_ARRIVAL):
+        eng = gv.Engine(geom, precision=p, queue_order=order)
+        e = eng.transport(prim, seed)
+        st = eng.stats()
+        out[order] = (e, st["steps"], st["tracks"], st["interactions"], eng.ledger())
+    a, b = out[gv.ORDER_STABLE], out[gv.ORDER_ARRIVAL]
+    assert a[1] == b[1] and a[2] == b[2] and a[3] == b[3]
+    assert np.allclose(a[0], b[0], rtol=1e-12, atol=1e-12 * max(1.0, a[0].max()))
+    assert np.allclose(a[4], b[4], rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("mode", ["arrival", "stable", "plain"])
+def test_capacity_overflow_restarts(gv, mode):
+    """Queues far too small for all events at once: the driver discards the
+    window on overflow, halves the events in flight and reruns; the result
+    equals the run with ample capacity."""
+    geom, prim, seed = gv_inputs.workload("c1", 40)
+    cfg = dict(precision=gv.P64)
+    if mode == "plain":
+        cfg["driver"] = gv.DRIVER_PLAIN
+    else:
+        cfg["queue_order"] = gv.ORDER_ARRIVAL if mode == "arrival" else gv.ORDER_STABLE
+    ref = gv.Engine(geom, **cfg).transport(prim, seed)
+    eng = gv.Engine(geom, capacity=256, **cfg)
+    e = eng.transport(prim, seed)
+    st = eng.stats()
+    print(f"\n[overflow {mode}] restarts {st['overflow_restarts']}")
+    assert st["overflow_restarts"] > 0
+    assert np.allclose(e, ref, rtol=1e-12, atol=1e-12 * max(1.0, ref.max()))
 
 
 def test_paired_layer_deposits_mixed_vs_oracle(gv, oracle_mod):
