@@ -30,6 +30,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "steps/s & primaries/s on 1 MI355X, FP32 batched vs FP64 plain, matched edep"
 HBM_PEAK = 8.0e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c4.json")
+
+
+def kernel_source_hash():
+    """SHA-1 over the HIP sources and build flags of the library."""
+    import hashlib
+    h = hashlib.sha1()
+    pkg = os.path.join(ROOT, "paper_2005_00949_amd")
+    files = sorted(os.listdir(os.path.join(pkg, "csrc")))
+    for f in files:
+        with open(os.path.join(pkg, "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(steps_per_launch, workload, knobs):
+    """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE counters
+    (per step, calibrated against a plain copy), or None when the kernel
+    sources changed since they were taken, or the workload or the knobs
+    (basket, occupancy, inner steps) differ."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_sha1") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("knobs") != list(knobs)):
+        return None
+    return t["bytes_per_step"] * steps_per_launch
 
 
 def log(msg):
@@ -72,16 +103,21 @@ def run_gpu(args):
     eng.stage(prim)
     log(f"[bench] workload {args.workload}: {len(prim)} primaries, {n_events} events, "
         f"{eng.n_cells} cells; warmup {args.warmup}, steps {args.steps}")
+    tune_ms = 0.0
     for w in range(args.warmup):
         eng.transport_staged(seed, edep.data_ptr())
         st = eng.stats()
-        log(f"[bench] warmup {w}: {st['transport_ms']:.1f} ms, {st['total_steps']} steps")
+        tune_ms += st["autotune_ms"]
+        log(f"[bench] warmup {w}: {st['transport_ms']:.1f} ms ({st['autotune_ms']:.1f} ms autotuning), "
+            f"{st['total_steps']} steps, basket {st['basket']} occupancy {st['occupancy']} "
+            f"inner {st['inner_steps']}")
     torch.cuda.synchronize()
     steps = prims = 0
     kernel_ms = 0.0
     launches = 0
     alg_bytes = 0.0
     edep_first = None
+    per_ms = []
     t0 = time.perf_counter()
     for k in range(args.steps):
         eng.transport_staged(seed + k, edep.data_ptr())
@@ -91,6 +127,7 @@ def run_gpu(args):
         kernel_ms += st["kernel_ms"]
         launches += st["kernel_launches"]
         alg_bytes += st["alg_bytes"]
+        per_ms.append(st["transport_ms"])
         if k == 0:
             edep_first = edep.cpu().numpy()
             st0 = st
@@ -98,7 +135,18 @@ def run_gpu(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
-               alg_bytes=alg_bytes, stats0=st0, n_events=n_events)
+               alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
+               autotune_ms=tune_ms)
+
+    # the same transport through gv_transport with host primaries and a host
+    # edep_out (PCIe both ways); reported beside value, never as value
+    eng.configure(edep_on_device=0)
+    t = time.perf_counter()
+    eng.transport(prim, seed)
+    res["pcie_inclusive_ms"] = (time.perf_counter() - t) * 1e3
+    res["pcie_inclusive_steps_per_s"] = eng.stats()["total_steps"] / (res["pcie_inclusive_ms"] * 1e-3)
+    eng.configure(edep_on_device=1)
+    eng.stage(prim)
 
     # plain FP64 per-stage path on the same batch and first seed
     plain = None
@@ -210,6 +258,10 @@ def main():
     bytes_per_launch = res["alg_bytes"] / max(res["launches"], 1)
     achieved = bytes_per_launch / avg_launch_s if avg_launch_s > 0 else 0.0
     st0 = res["stats0"]
+    steps_per_launch = res["steps"] / max(res["launches"], 1)
+    workload_id = f"{args.workload}x{res['primaries'] // args.steps}"
+    traffic = measured_traffic(steps_per_launch, workload_id,
+                               (st0["basket"], st0["occupancy"], st0["inner_steps"]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -231,17 +283,23 @@ def main():
             "driver": "batched persistent kernel, graph-captured step loop",
             "precision": "mixed: FP32 physics/tables/direction/energy, FP64 position/boundary/deposit",
             "basket": st0["basket"], "occupancy": st0["occupancy"], "inner_steps": st0["inner_steps"],
-            "graph_steps": st0["graph_steps"]},
+            "graph_steps": st0["graph_steps"], "autotuned": bool(st0["tuned"]),
+            "queue_order": "stable" if st0["queue_order"] else "arrival"},
         "primaries_per_s": res["primaries"] / res["elapsed"],
+        "median_ms_per_transport": res["median_ms"],
+        "autotune_ms": res["autotune_ms"],
+        "pcie_inclusive": {"ms_per_transport": res["pcie_inclusive_ms"],
+                           "steps_per_s": res["pcie_inclusive_steps_per_s"]},
         "track_steps_per_transport": res["steps"] / args.steps,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (value / plain["steps_per_s"]) if plain else None,
         "batched_fp64": b64,
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
-                     "kernel": "k_step_batched<PMix,256>",
+                     "frac": achieved / HBM_PEAK, "traffic": traffic,
+                     "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),
                      "avg_launch_us": avg_launch_s * 1e6, "alg_bytes_per_launch": bytes_per_launch,
-                     "launches": res["launches"]},
+                     "steps_per_launch": steps_per_launch, "launches": res["launches"],
+                     "kernel_source_sha1": kernel_source_hash()},
         "cpu_baseline": cpu,
     }
     line = json.dumps(out)

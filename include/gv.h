@@ -125,7 +125,12 @@ typedef struct {
     int32_t precision;              /* GV_P64 or GV_PMIX; PLAIN supports GV_P64 only */
     int32_t basket;                 /* tracks per claimed basket, 64..4096 (power of 2), 0 = tuned */
     int32_t occupancy;              /* workgroups per CU of the persistent kernel, 0 = tuned */
-    int32_t inner_steps;            /* max steps a track takes in registers per launch, 0 = tuned */
+    int32_t inner_steps;            /* max steps a track takes in registers per launch, 0 = tuned.
+                                       Knobs left at 0 are chosen by the autotuner for batches
+                                       of >= 4096 primaries (trial transports of a sample of
+                                       the batch, choice cached per precision, order and batch
+                                       size class), otherwise they take the defaults
+                                       256 / 4 / 4 */
     int32_t graph_steps;            /* step launches per captured graph, 0 = default */
     int32_t field_method;           /* GV_FIELD_HELIX or GV_FIELD_RK4 */
     int32_t edep_on_device;         /* edep_out of gv_transport is a device pointer */
@@ -158,9 +163,18 @@ typedef struct {
     double init_ms;                 /* wall time of gv_init (tables, uploads) */
     double kernel_ms;               /* summed duration of the step kernels (HIP events) */
     int64_t kernel_launches;        /* step-kernel launches timed into kernel_ms */
-    double alg_bytes;               /* algorithmic HBM bytes of track state moved */
+    double alg_bytes;               /* algorithmic track-state bytes: per step one slot read
+                                       and the moving fields written back (PMix 60 + 48 B,
+                                       FP64 77 + 64 B), plus one slot per secondary */
     int32_t driver, precision, basket, occupancy, inner_steps, graph_steps;
     int64_t capacity;
+    double state_bytes;             /* track-state bytes the step kernels actually moved
+                                       (slot reads + slot writes) */
+    double autotune_ms;             /* time spent choosing basket/occupancy/inner steps
+                                       before this transport (0 if a cached choice was used) */
+    int32_t tuned;                  /* 1: basket/occupancy/inner steps left at 0 were set by
+                                       the autotuner, 0: defaults or caller's values */
+    int32_t queue_order;
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

@@ -73,7 +73,8 @@ class Stats(C.Structure):
                 ("kernel_launches", C.c_int64), ("alg_bytes", C.c_double),
                 ("driver", C.c_int32), ("precision", C.c_int32), ("basket", C.c_int32),
                 ("occupancy", C.c_int32), ("inner_steps", C.c_int32), ("graph_steps", C.c_int32),
-                ("capacity", C.c_int64)]
+                ("capacity", C.c_int64), ("state_bytes", C.c_double), ("autotune_ms", C.c_double),
+                ("tuned", C.c_int32), ("queue_order", C.c_int32)]
 
 
 class DebugIO(C.Structure):

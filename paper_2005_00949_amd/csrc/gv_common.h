@@ -51,7 +51,26 @@ struct PMix {
 // Overloaded device math so that stage code is written once per policy.  The
 // double versions are the accurate library functions; the float versions use
 // the gfx950 hardware transcendentals (log2/exp2/sin/cos units, a few ulp),
-// which keep every single-step output within its 1e-5 budget.
+// which keep every single-step output within its 1e-5 budget.  Sine and
+// cosine are the exception on |x| <= pi/4: the hardware units have an
+// absolute error near 5e-7 there, i.e. a large relative error for the small
+// angles that dominate (scattering angles, pair opening angles, the helix
+// phase of one step), and those errors decorrelate mixed-precision histories
+// from their FP64 twins; there the Taylor polynomials through x^9 and x^10
+// (truncation below 3e-9 relative at pi/4) are used instead.
+
+__device__ __forceinline__ float sin_small(float x)
+{
+    const float x2 = x * x;
+    return x * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f)))));
+}
+__device__ __forceinline__ float cos_small(float x)
+{
+    const float x2 = x * x;
+    return 1.0f + x2 * (-0.5f + x2 * (1.0f / 24.0f + x2 * (-1.0f / 720.0f + x2 * (1.0f / 40320.0f +
+                                                                                   x2 * (-1.0f / 3628800.0f)))));
+}
+constexpr float kQuarterPi = 0.78539816f;
 __device__ __forceinline__ double m_log(double x) { return log(x); }
 __device__ __forceinline__ float m_log(float x) { return __logf(x); }
 __device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
@@ -63,9 +82,9 @@ __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double m_sin(double x) { return sin(x); }
-__device__ __forceinline__ float m_sin(float x) { return __sinf(x); }
+__device__ __forceinline__ float m_sin(float x) { return fabsf(x) <= kQuarterPi ? sin_small(x) : __sinf(x); }
 __device__ __forceinline__ double m_cos(double x) { return cos(x); }
-__device__ __forceinline__ float m_cos(float x) { return __cosf(x); }
+__device__ __forceinline__ float m_cos(float x) { return fabsf(x) <= kQuarterPi ? cos_small(x) : __cosf(x); }
 __device__ __forceinline__ double m_atan2(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float m_atan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }

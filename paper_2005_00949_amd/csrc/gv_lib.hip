@@ -14,12 +14,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "gv_kernels.h"
@@ -127,11 +130,13 @@ struct GraphKey {
     const void* trace = nullptr;
     long long trace_cap = 0;
     int order = -1;
+    int grid = 0, tail_grid = 0, tail_K = 0;
     bool operator==(const GraphKey& o) const
     {
         return prec == o.prec && block == o.block && chunks == o.chunks && inner_bulk == o.inner_bulk &&
                inner_tail == o.inner_tail && K == o.K && tail == o.tail && cap == o.cap && qblock == o.qblock &&
-               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order;
+               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order &&
+               grid == o.grid && tail_grid == o.tail_grid && tail_K == o.tail_K;
     }
 };
 
@@ -190,6 +195,11 @@ struct Lib {
     bool staged = false;
     size_t staged_b = 0, staged_e = 0;   // window whose queue slots are on the device
     bool staged_one_queue = false;       // ... laid out for one mixed pool (plain) or per type
+    // autotuner choices, per (precision, queue order, log2 of the batch size);
+    // cleared by gv_init
+    std::map<std::tuple<int, int, int>, std::array<int, 3>> tune_cache;
+    double autotune_ms = 0.0;
+    bool tuned = false;
 };
 
 Lib L;
@@ -270,6 +280,7 @@ void release_all()
     L.staged = false;
     L.hp.clear();
     L.ev_start.clear();
+    L.tune_cache.clear();
     L.ready = false;
 }
 
@@ -419,20 +430,25 @@ struct Tuning {
     int tail_K;          // launches per tail graph replay
 };
 
-Tuning pick_tuning(int n_primaries)
+// default knob values, used for small batches and as the autotuner's start
+constexpr int kDefBasket = 256, kDefOccupancy = 4, kDefInner = 4;
+// batches below this many primaries are not autotuned
+constexpr int64_t kTuneMinPrimaries = 4096;
+
+// knob values: the caller's where set, else `choice` (basket, occupancy, inner)
+Tuning pick_tuning(const std::array<int, 3>& choice)
 {
     Tuning t;
-    const int basket = L.cfg.basket ? L.cfg.basket : 256;
+    const int basket = L.cfg.basket ? L.cfg.basket : choice[0];
     t.block = basket >= 256 ? 256 : basket;
     t.chunks = basket / t.block;
-    t.occupancy = L.cfg.occupancy ? L.cfg.occupancy : 4;
-    t.inner_bulk = L.cfg.inner_steps ? L.cfg.inner_steps : 4;
+    t.occupancy = L.cfg.occupancy ? L.cfg.occupancy : choice[1];
+    t.inner_bulk = L.cfg.inner_steps ? L.cfg.inner_steps : choice[2];
     t.inner_tail = std::max(t.inner_bulk, 256);
     t.K = L.cfg.graph_steps ? L.cfg.graph_steps : 16;
     t.tail = (uint32_t)std::min<long long>((long long)L.n_cu * t.block * 2, 1u << 30);
     t.tail_grid = t.occupancy * L.n_cu;
     t.tail_K = 4 * t.K;
-    (void)n_primaries;
     return t;
 }
 
@@ -641,6 +657,9 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     key.trace = L.cfg.trace_cap > 0 ? L.trace.p : nullptr;
     key.trace_cap = L.cfg.trace_cap;
     key.order = L.cfg.queue_order;
+    key.grid = tu.occupancy * L.n_cu;
+    key.tail_grid = tu.tail_grid;
+    key.tail_K = tu.tail_K;
     if (!L.gexec || !(L.gkey == key)) {
         rc = build_graph<P>(tu, key);
         if (rc) return rc;
@@ -768,6 +787,106 @@ int type_of_pdg(int pdg)
     return pdg == 22 ? kGamma : pdg == 11 ? kElectron : pdg == -11 ? kPositron : -1;
 }
 
+// zero the per-run device accumulators (deposits, ledger, counters, trace)
+int reset_run_buffers(int64_t n_events)
+{
+    hipStream_t s = stream();
+    const size_t nc = (size_t)std::max(L.n_cells, 1);
+    HIPCHK(hipMemsetAsync(L.edep.p, 0, (size_t)n_events * nc * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(L.ledger.p, 0, (size_t)n_events * 4 * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(L.counters.p, 0, kNCount * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(L.trace_n.p, 0, sizeof(unsigned long long), s));
+    return GV_OK;
+}
+
+// Autotuner for the knobs the caller left at 0 (basket, occupancy, inner
+// steps).  Trial transports of a sample of the staged batch (its first
+// events, at least 1024 primaries, about an eighth of the batch) are timed by
+// step-kernel time; coordinate search over inner steps, then basket, then
+// occupancy, from the defaults.  The choice is cached per precision, queue
+// order and batch-size class; the trials' deposits and counters are discarded.
+template <class P> int tuned_choice(int64_t n_events, uint64_t seed, std::array<int, 3>& choice)
+{
+    L.tuned = false;
+    L.autotune_ms = 0.0;
+    const bool free_knob = !L.cfg.basket || !L.cfg.occupancy || !L.cfg.inner_steps;
+    if (!free_knob || L.n_prim < kTuneMinPrimaries) return GV_OK;
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= L.n_prim) ++lg;
+    const auto key = std::make_tuple((int)P::kMixed, (int)L.cfg.queue_order, lg);
+    auto it = L.tune_cache.find(key);
+    if (it != L.tune_cache.end()) {
+        choice = it->second;
+        L.tuned = true;
+        return GV_OK;
+    }
+    const double t0 = now_ms();
+    int64_t ne = std::max<int64_t>(1, n_events / 8);
+    while (ne < n_events && L.ev_start[ne] < 1024) ne = std::min(n_events, 2 * ne);
+    const size_t cap = batch_cap<P>();
+    const uint64_t tseed = seed ^ 0x6175746f74756e65ull;
+    auto trial = [&](const std::array<int, 3>& c, double& rate) -> int {
+        const Tuning tu = pick_tuning(c);
+        int rc = ensure_status(cap, tu.block);
+        if (rc) return rc;
+        rc = reset_run_buffers(ne);
+        if (rc) return rc;
+        L.stats.iterations = 0;
+        const double k0 = L.stats.kernel_ms;
+        rc = run_batched_window<P>(L.ev_start[0], L.ev_start[ne], tseed, tu);
+        if (rc == GV_E_CAPACITY) {
+            rate = 0.0;
+            return GV_OK;
+        }
+        if (rc) return rc;
+        unsigned long long cnt[kNCount];
+        HIPCHK(hipMemcpyAsync(cnt, L.counters.p, sizeof(cnt), hipMemcpyDeviceToHost, stream()));
+        HIPCHK(hipStreamSynchronize(stream()));
+        const double ms = L.stats.kernel_ms - k0;
+        rate = ms > 0.0 ? (double)(cnt[kCSteps] + cnt[kCSteps + 1] + cnt[kCSteps + 2]) / ms : 0.0;
+        if (L.progress)
+            std::fprintf(stderr, "[gv] autotune basket %d occupancy %d inner %d: %.4g steps/ms\n", c[0], c[1], c[2],
+                         rate);
+        return GV_OK;
+    };
+    std::array<int, 3> best = choice;
+    double best_rate = 0.0;
+    int rc = trial(best, best_rate);
+    if (rc) return rc;
+    static const int kCand[3][4] = {{64, 128, 256, 512}, {1, 2, 4, 8}, {1, 2, 4, 8}};
+    const int fixed[3] = {L.cfg.basket, L.cfg.occupancy, L.cfg.inner_steps};
+    for (int knob : {2, 0, 1}) {
+        if (fixed[knob]) continue;
+        const std::array<int, 3> base = best;
+        for (int v : kCand[knob]) {
+            if (v == base[knob]) continue;
+            std::array<int, 3> c = base;
+            c[knob] = v;
+            double r = 0.0;
+            rc = trial(c, r);
+            if (rc) return rc;
+            if (r > best_rate) {
+                best_rate = r;
+                best = c;
+            }
+        }
+    }
+    choice = best;
+    L.tune_cache[key] = best;
+    L.tuned = true;
+    L.autotune_ms = now_ms() - t0;
+    // discard the trials' results; the transport proper starts clean
+    rc = reset_run_buffers(n_events);
+    if (rc) return rc;
+    const double init_ms = L.stats.init_ms;
+    const int32_t drv = L.stats.driver, prec = L.stats.precision;
+    L.stats = gv_stats_t{};
+    L.stats.init_ms = init_ms;
+    L.stats.driver = drv;
+    L.stats.precision = prec;
+    return GV_OK;
+}
+
 template <class P> int transport_batched(int64_t n_events, uint64_t seed)
 {
     const std::vector<size_t>& ev_start = L.ev_start;
@@ -780,8 +899,11 @@ template <class P> int transport_batched(int64_t n_events, uint64_t seed)
         L.qmix.release();
         HIPCHK(Q.alloc(cap, 6, false));
     }
-    const Tuning tu = pick_tuning((int)L.n_prim);
-    int rc = ensure_status(cap, tu.block);
+    std::array<int, 3> choice{kDefBasket, kDefOccupancy, kDefInner};
+    int rc = tuned_choice<P>(n_events, seed, choice);
+    if (rc) return rc;
+    const Tuning tu = pick_tuning(choice);
+    rc = ensure_status(cap, tu.block);
     if (rc) return rc;
     L.stats.basket = tu.block * tu.chunks;
     L.stats.occupancy = tu.occupancy;
@@ -1027,12 +1149,11 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     int rc = ensure_common(n_events);
     if (rc) return rc;
     hipStream_t s = stream();
-    const size_t nc = (size_t)std::max(L.n_cells, 1);
-    HIPCHK(hipMemsetAsync(L.edep.p, 0, (size_t)n_events * nc * sizeof(double), s));
-    HIPCHK(hipMemsetAsync(L.ledger.p, 0, (size_t)n_events * 4 * sizeof(double), s));
-    HIPCHK(hipMemsetAsync(L.counters.p, 0, kNCount * sizeof(unsigned long long), s));
-    HIPCHK(hipMemsetAsync(L.trace_n.p, 0, sizeof(unsigned long long), s));
+    rc = reset_run_buffers(n_events);
+    if (rc) return rc;
     L.stats = gv_stats_t{};
+    L.autotune_ms = 0.0;
+    L.tuned = false;
     L.plain_loads = L.plain_stores = 0.0;
     L.stats.init_ms = L.init_ms;
     L.stats.driver = L.cfg.driver;
@@ -1083,14 +1204,31 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     L.stats.e_killed = ek;
     L.stats.n_pair = np_;
     L.stats.n_annih = na;
-    // track-state bytes the step kernels must move: one slot read per track per
-    // launch, one slot written per survivor and per secondary
+    // algorithmic track-state bytes: per step one slot read and the moving
+    // fields (position, direction, energy, volume, step count) written back;
+    // one slot written per secondary
+    {
+        const bool mixed = L.cfg.driver == GV_DRIVER_BATCHED && L.cfg.precision == GV_PMIX;
+        const double per_step = mixed ? 60.0 + 48.0 : 77.0 + 64.0;
+        const double per_child = mixed ? 60.0 : 77.0;
+        double steps = 0.0, children = 0.0;
+        for (int t = 0; t < 3; ++t) {
+            steps += (double)L.stats.steps[t];
+            children += (double)(L.stats.tracks[t] - L.tracks0[t]);
+        }
+        L.stats.alg_bytes = per_step * steps + per_child * children;
+    }
+    // track-state bytes the step kernels actually moved: one slot read per
+    // track per launch, one slot written per survivor and per secondary
     if (L.cfg.driver == GV_DRIVER_BATCHED) {
         const double slot_bytes = L.cfg.precision == GV_PMIX ? 60.0 : 76.0;
-        L.stats.alg_bytes = (double)(cnt[kCLoads] + cnt[kCStores]) * slot_bytes;
+        L.stats.state_bytes = (double)(cnt[kCLoads] + cnt[kCStores]) * slot_bytes;
     } else {  // the mixed pool carries a type byte
-        L.stats.alg_bytes = (L.plain_loads + L.plain_stores) * 77.0;
+        L.stats.state_bytes = (L.plain_loads + L.plain_stores) * 77.0;
     }
+    L.stats.autotune_ms = L.autotune_ms;
+    L.stats.tuned = L.tuned ? 1 : 0;
+    L.stats.queue_order = L.cfg.queue_order;
     L.stats.transport_ms = now_ms() - t0;
     return GV_OK;
 }

@@ -205,3 +205,29 @@ def test_staged_batch_reused_across_drivers(gv, oracle_mod):
             assert np.allclose(e, ref["edep"], rtol=1e-8, atol=1e-8 * scale), cfg
         else:
             assert abs(st["total_steps"] / n_ref - 1) < 0.01, (cfg, st["total_steps"], n_ref)
+
+
+def test_autotuner_choice_is_cached_and_exact(gv):
+    """Knobs left at 0 on a batch of >= 4096 primaries are chosen by trial
+    transports of a sample; the choice is cached, and the transport with the
+    chosen knobs equals one with the same knobs given explicitly."""
+    geom, prim, seed = gv_inputs.workload("c1", 4200)
+    eng = gv.Engine(geom, precision=gv.P64)
+    e1 = eng.transport(prim, seed)
+    st1 = eng.stats()
+    assert st1["tuned"] == 1 and st1["autotune_ms"] > 0
+    assert st1["basket"] in (64, 128, 256, 512) and st1["occupancy"] in (1, 2, 4, 8)
+    assert st1["inner_steps"] in (1, 2, 4, 8)
+    e2 = eng.transport(prim, seed)
+    st2 = eng.stats()
+    assert st2["tuned"] == 1 and st2["autotune_ms"] == 0
+    assert (st2["basket"], st2["occupancy"], st2["inner_steps"]) == (st1["basket"], st1["occupancy"],
+                                                                      st1["inner_steps"])
+    fixed = gv.Engine(geom, precision=gv.P64, basket=st1["basket"], occupancy=st1["occupancy"],
+                      inner_steps=st1["inner_steps"])
+    e3 = fixed.transport(prim, seed)
+    st3 = fixed.stats()
+    assert st3["tuned"] == 0 and st3["total_steps"] == st1["total_steps"]
+    scale = max(1.0, e3.max())
+    assert np.allclose(e1, e3, rtol=1e-12, atol=1e-12 * scale)
+    assert np.allclose(e2, e3, rtol=1e-12, atol=1e-12 * scale)
