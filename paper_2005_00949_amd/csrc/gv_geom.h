@@ -11,6 +11,10 @@
 //
 // Every distance also names the plane face it ends on (axis, value) so that a
 // straight boundary-limited step places the point exactly on the plane.
+// Plane distances are kept as numerator / |direction component| and compared
+// by cross-multiplication; only the chosen one is divided out, which gives the
+// same quotient as dividing every candidate (FP64 division is a long
+// instruction sequence on gfx950, and the world query needs up to nine).
 // Ties between faces resolve in the order x-, x+, y-, y+, z-, z+ (shells:
 // inner, outer, z-, z+) with strict comparisons.  All arithmetic is double:
 // positions and boundaries stay FP64 under every precision policy, and is not
@@ -34,6 +38,8 @@ struct DevGeom {
     double world[4];
     double B[3];
     double Bmag;
+    double Bhat[3];               // B / |B| (0 when there is no field)
+    double kB;                    // kKB * |B|: curvature per unit momentum, 1/(cm MeV)
     double bounds[GV_MAX_VOLS + 1];
     int vmat[GV_MAX_VOLS];
     int vcell[GV_MAX_VOLS];
@@ -87,18 +93,23 @@ __device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], cons
 #pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[v - 1]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[v]};
-    double best = kInf, plane = hi[2];
+    double bn = 1.0, bd = 0.0;    // nearest face so far at bn / bd; bd == 0: none yet
+    double plane = hi[2];
     int face = 5;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] < 0.0) {
-            const double t = (lo[a] - p[a]) / d[a];
-            if (t < best) { best = t; face = 2 * a; plane = lo[a]; }
-        } else if (d[a] > 0.0) {
-            const double t = (hi[a] - p[a]) / d[a];
-            if (t < best) { best = t; face = 2 * a + 1; plane = hi[a]; }
+        if (d[a] == 0.0) continue;
+        const bool up = d[a] > 0.0;
+        const double n = up ? hi[a] - p[a] : p[a] - lo[a];
+        const double den = up ? d[a] : -d[a];
+        if (bd == 0.0 || n * bd < bn * den) {
+            bn = n;
+            bd = den;
+            face = 2 * a + (up ? 1 : 0);
+            plane = up ? hi[a] : lo[a];
         }
     }
+    const double best = bd > 0.0 ? bn / bd : kInf;
     Hit h;
     h.t = best > 0.0 ? best : 0.0;
     h.next = face == 4 ? (v == 1 ? 0 : v - 1) : face == 5 ? (v == g.n_vol ? 0 : v + 1) : 0;
@@ -121,27 +132,41 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
 #pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
-    double tn = -kInf, tf = kInf, plane = 0.0;
+    // entry (max of near-plane distances) and exit (min of far-plane
+    // distances) of the ray's parameter interval inside the envelope box
+    double nn = 0.0, nd = 0.0, fn = 0.0, fd = 0.0, plane = 0.0;
     int an = -1;
-    bool miss = false;
+    bool miss = false, have = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] == 0.0) {
             miss = miss || p[a] < lo[a] || p[a] > hi[a];
-        } else {
-            const double t1 = (lo[a] - p[a]) / d[a], t2 = (hi[a] - p[a]) / d[a];
-            const double tmin = fmin(t1, t2), tmax = fmax(t1, t2);
-            if (tmin > tn) { tn = tmin; an = a; plane = d[a] > 0.0 ? lo[a] : hi[a]; }
-            if (tmax < tf) tf = tmax;
+            continue;
         }
+        const bool up = d[a] > 0.0;
+        const double den = up ? d[a] : -d[a];
+        const double n_near = up ? lo[a] - p[a] : p[a] - hi[a];
+        const double n_far = up ? hi[a] - p[a] : p[a] - lo[a];
+        if (!have || n_near * nd > nn * den) {
+            nn = n_near;
+            nd = den;
+            an = a;
+            plane = up ? lo[a] : hi[a];
+        }
+        if (!have || n_far * fd < fn * den) {
+            fn = n_far;
+            fd = den;
+        }
+        have = true;
     }
     Hit h;
     h.t = kInf;
     h.next = 0;
     h.snap_axis = -1;
     h.snap_val = 0.0;
-    if (!miss && tn <= tf && tf > 0.0) {
-        if (tn > 0.0) {
+    if (have && !miss && nn * fd <= fn * nd && fn > 0.0) {
+        if (nn > 0.0) {
+            const double tn = nn / nd;
             h.t = tn;
             h.snap_axis = an;
             h.snap_val = plane;
@@ -151,16 +176,22 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
             h.next = stack_of(g, p[2]);
         }
     }
+    // leaving the world box: the nearest far plane
     const double wlo[3] = {-g.world[0], -g.world[1], g.world[2]};
     const double whi[3] = {g.world[0], g.world[1], g.world[3]};
-    double tw = kInf;
+    double wn = 1.0, wd = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double t = kInf;
-        if (d[a] < 0.0) t = (wlo[a] - p[a]) / d[a];
-        else if (d[a] > 0.0) t = (whi[a] - p[a]) / d[a];
-        tw = t < tw ? t : tw;
+        if (d[a] == 0.0) continue;
+        const bool up = d[a] > 0.0;
+        const double n = up ? whi[a] - p[a] : p[a] - wlo[a];
+        const double den = up ? d[a] : -d[a];
+        if (wd == 0.0 || n * wd < wn * den) {
+            wn = n;
+            wd = den;
+        }
     }
+    double tw = wd > 0.0 ? wn / wd : kInf;
     tw = tw > 0.0 ? tw : 0.0;
     if (!(h.t <= tw)) {
         h.t = tw;

@@ -151,6 +151,69 @@ __device__ __forceinline__ void deposit(const Sinks& S, uint32_t ev, int vol, do
     else unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], e);
 }
 
+// Per-workgroup deposit cache (batched driver): an open-addressed table in LDS
+// keyed by event * n_cells + cell.  Deposits of a chunk's tracks land there
+// with LDS atomics and go to HBM once per (event, cell) when the chunk's
+// inner loop is done, instead of one HBM atomic per track and volume.  Keys
+// that do not fit 32 bits, or that find no free slot within a few probes, go
+// straight to HBM.
+constexpr int kDepSlots = 512;
+constexpr int kDepProbes = 8;
+constexpr uint32_t kDepEmpty = 0xFFFFFFFFu;
+struct DepCache {
+    uint32_t key[kDepSlots];
+    double val[kDepSlots];
+};
+
+template <int BLOCK> __device__ __forceinline__ void dep_clear(DepCache& dc)
+{
+    for (int i = threadIdx.x; i < kDepSlots; i += BLOCK) {
+        dc.key[i] = kDepEmpty;
+        dc.val[i] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void dep_add(DepCache& dc, const Sinks& S, uint32_t ev, int vol, double e)
+{
+    if (e == 0.0) return;
+    const int cell = vol_cell(c_geom, vol);
+    if (cell < 0) {
+        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], e);
+        return;
+    }
+    const uint64_t k64 = (uint64_t)ev * (uint64_t)c_geom.n_cells + (uint64_t)cell;
+    if (k64 < kDepEmpty) {
+        const uint32_t k = (uint32_t)k64;
+        uint32_t h = (k * 2654435761u) >> 23;   // 9 bits: kDepSlots = 512
+        for (int probe = 0; probe < kDepProbes; ++probe) {
+            const uint32_t old = atomicCAS(&dc.key[h], kDepEmpty, k);
+            if (old == kDepEmpty || old == k) {
+                // explicit LDS address space: the add must be a ds atomic
+                typedef __attribute__((address_space(3))) double lds_double;
+                __hip_atomic_fetch_add((lds_double*)&dc.val[h], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            h = (h + 1) & (kDepSlots - 1);
+        }
+    }
+    unsafeAtomicAdd(&S.edep[k64], e);
+}
+
+// write the cached sums to HBM and empty the cache (all threads call it)
+template <int BLOCK> __device__ __forceinline__ void dep_flush(DepCache& dc, const Sinks& S)
+{
+    __syncthreads();
+    for (int i = threadIdx.x; i < kDepSlots; i += BLOCK) {
+        const uint32_t k = dc.key[i];
+        if (k != kDepEmpty) {
+            unsafeAtomicAdd(&S.edep[k], dc.val[i]);
+            dc.key[i] = kDepEmpty;
+            dc.val[i] = 0.0;
+        }
+    }
+    __syncthreads();
+}
+
 // ===========================================================================
 // Table builder (FP64 on the device)
 // ===========================================================================
@@ -520,8 +583,8 @@ __device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[
 template <class P, int TY, int BLOCK, bool STABLE, class R = typename P::R>
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
-                                              unsigned* cnt_lds, uint32_t& steps_here, uint32_t& loads,
-                                              uint32_t& stores, uint32_t n_chunks)
+                                              DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
+                                              uint32_t& loads, uint32_t& stores, uint32_t n_chunks)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -542,7 +605,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             step_track(c, t, o);
             steps_here += o.did_step;
             if (o.vol_pre != acc_vol) {
-                deposit(A.S, t.ev, acc_vol, acc);
+                dep_add(dc, A.S, t.ev, acc_vol, acc);
                 acc = 0.0;
                 acc_vol = o.vol_pre;
             }
@@ -551,8 +614,9 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             account_rare(A.S, t.ev, o, cnt_lds);
             if (o.status != kAlive || o.nchild > 0) break;
         }
-        deposit(A.S, t.ev, acc_vol, acc);
+        dep_add(dc, A.S, t.ev, acc_vol, acc);
     }
+    dep_flush<BLOCK>(dc, A.S);
     const int alive = (active && o.status == kAlive) ? 1 : 0;
     const int q1 = o.nchild > 0 ? o.ch[0].type : -1;
     const int q2 = o.nchild > 1 ? o.ch[1].type : -1;
@@ -605,7 +669,9 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
 {
     __shared__ ScanShared<BLOCK> sh;
     __shared__ unsigned cnt_lds[kNCount];
+    __shared__ DepCache dc;
     for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
+    dep_clear<BLOCK>(dc);
 
     const int pin = A.parity;
     // after an overflow (reported to the host, which reruns the window) the
@@ -640,13 +706,13 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
         const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
-                process_chunk<P, kGamma, BLOCK, STABLE>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, cnt_lds, steps_g,
+                process_chunk<P, kGamma, BLOCK, STABLE>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
                                                 loads, stores, n_chunks);
             else if (chunk < c0 + c1)
-                process_chunk<P, kElectron, BLOCK, STABLE>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, cnt_lds,
+                process_chunk<P, kElectron, BLOCK, STABLE>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
                                                    steps_e, loads, stores, n_chunks);
             else
-                process_chunk<P, kPositron, BLOCK, STABLE>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh,
+                process_chunk<P, kPositron, BLOCK, STABLE>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
                                                    cnt_lds, steps_p, loads, stores, n_chunks);
         }
     }

@@ -1002,6 +1002,8 @@ int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom, co
     for (int i = 0; i < 4; ++i) g.world[i] = geom->world[i];
     for (int i = 0; i < 3; ++i) g.B[i] = geom->B[i];
     g.Bmag = std::sqrt(g.B[0] * g.B[0] + g.B[1] * g.B[1] + g.B[2] * g.B[2]);
+    for (int i = 0; i < 3; ++i) g.Bhat[i] = g.Bmag > 0.0 ? g.B[i] / g.Bmag : 0.0;
+    g.kB = kKB * g.Bmag;
     if (g.axis == GV_AXIS_Z_SLABS) {
         if (!(g.env[0] > 0 && g.env[1] > 0 && g.world[0] >= g.env[0] && g.world[1] >= g.env[1] &&
               g.world[2] <= g.bounds[0] && g.world[3] >= g.bounds[g.n_vol]))

@@ -341,18 +341,20 @@ template <class R> __device__ inline bool sample_bhabha(R T, R tc, const Key& ke
 // increment and the direction are computed in the policy's precision.
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ inline void helix_move(int type, R T, const double B[3], double Bmag, double s, double pos[3], R u[3])
+__device__ inline void helix_move(int type, R T, const double Bhat[3], double kB, double s, double pos[3], R u[3])
 {
 #pragma clang fp contract(off)
     // The turning angle is formed and reduced to [-pi, pi] in double so that
     // long steps keep their phase; trigonometry of the reduced angle and the
-    // direction update run in the policy's precision.
+    // direction update run in the policy's precision.  kB = kKB |B| and
+    // Bhat = B / |B| are formed once at set-up (q kKB |B| is the same double
+    // either way, q being +-1).
     const double q = type == kElectron ? -1.0 : 1.0;
     const double Td = (double)T;
     const double p = sqrt(Td * (Td + 2.0 * kMe));
-    const double th = -(q * kKB * Bmag / p) * s;
-    const double thr = sizeof(R) == sizeof(double) ? th : th - 2.0 * kPi * rint(th / (2.0 * kPi));
-    const R b[3] = {(R)(B[0] / Bmag), (R)(B[1] / Bmag), (R)(B[2] / Bmag)};
+    const double th = -(q * kB / p) * s;
+    const double thr = sizeof(R) == sizeof(double) ? th : th - 2.0 * kPi * rint(th * (0.5 / kPi));
+    const R b[3] = {(R)Bhat[0], (R)Bhat[1], (R)Bhat[2]};
     const R upar = u[0] * b[0] + u[1] * b[1] + u[2] * b[2];
     const R up[3] = {u[0] - upar * b[0], u[1] - upar * b[1], u[2] - upar * b[2]};
     const R bxu[3] = {b[1] * up[2] - b[2] * up[1], b[2] * up[0] - b[0] * up[2], b[0] * up[1] - b[1] * up[0]};

@@ -182,15 +182,20 @@ __device__ inline bool stage_prestep(const Ctx<P>& c, Track<P>& t, StepOut<R>& o
 template <class P, class R = typename P::R>
 __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>& L)
 {
-    const U4 b0 = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpStep);
     const int m = vol_material(*c.g, t.vol);
     L.m = m;
     L.sa = (R)0;
     L.stot = (R)0;
     L.range = (R)0;
     L.s_eloss = big_len<R>();
+    L.usel = (R)0;
+    L.s_phys = big_len<R>();
+    // vacuum has no process: its STEP block is never needed (the streams are
+    // counter-based, so not drawing it changes no other number)
+    if (m < 0) return;
+    const U4 b0 = stream_block(c.seed, t.ev, t.tid, t.nstep, kPurpStep);
     L.usel = u53<R>(b0.w[2], b0.w[3]);
-    if (m >= 0) {
+    {
         const R* base = tab_base(c.tv, m, t.type);
         const int i = find_bin(c.tv, t.T, c.ph->log10_emin, c.ph->bpd);
         const R w = (t.T - c.tv.E[i]) / (c.tv.E[i + 1] - c.tv.E[i]);
@@ -251,12 +256,12 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     // charged particle in a uniform field
     const R p = m_sqrt(t.T * (t.T + (R)(2.0 * kMe)));
     // sine of the pitch angle from |u x b| (no cancellation near 0 or pi)
-    const R bx = (R)(g.B[0] / g.Bmag), by = (R)(g.B[1] / g.Bmag), bz = (R)(g.B[2] / g.Bmag);
+    const R bx = (R)g.Bhat[0], by = (R)g.Bhat[1], bz = (R)g.Bhat[2];
     const R cx = t.u[1] * bz - t.u[2] * by, cy = t.u[2] * bx - t.u[0] * bz, cz = t.u[0] * by - t.u[1] * bx;
     const R sin2 = cx * cx + cy * cy + cz * cz;
     double rcurv = kInf, dfield = kInf;
     if (sin2 > (R)0) {
-        const R rc = p / ((R)(kKB * g.Bmag) * m_sqrt(sin2));
+        const R rc = p / ((R)g.kB * m_sqrt(sin2));
         rcurv = (double)rc;
         dfield = (double)m_sqrt((R)2 * rc * (R)c.ph->chord_tol);
     }
@@ -275,7 +280,7 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
         nsub = nsub < 1.0 ? 1.0 : (nsub > 100000.0 ? 100000.0 : nsub);
         rk4_move<R>(t.type, t.T, g.B, pr.s, (int)nsub, t.x, t.u);
     } else {
-        helix_move<R>(t.type, t.T, g.B, g.Bmag, pr.s, t.x, t.u);
+        helix_move<R>(t.type, t.T, g.Bhat, g.kB, pr.s, t.x, t.u);
     }
     const int nv = locate(g, t.x);
     if (nv != t.vol) {
