@@ -140,13 +140,15 @@ def run_gpu(args):
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
-    eng.configure(edep_on_device=0)
-    t = time.perf_counter()
-    eng.transport(prim, seed)
-    res["pcie_inclusive_ms"] = (time.perf_counter() - t) * 1e3
-    res["pcie_inclusive_steps_per_s"] = eng.stats()["total_steps"] / (res["pcie_inclusive_ms"] * 1e-3)
-    eng.configure(edep_on_device=1)
-    eng.stage(prim)
+    res["pcie_inclusive_ms"] = res["pcie_inclusive_steps_per_s"] = None
+    if not args.no_pcie:
+        eng.configure(edep_on_device=0)
+        t = time.perf_counter()
+        eng.transport(prim, seed)
+        res["pcie_inclusive_ms"] = (time.perf_counter() - t) * 1e3
+        res["pcie_inclusive_steps_per_s"] = eng.stats()["total_steps"] / (res["pcie_inclusive_ms"] * 1e-3)
+        eng.configure(edep_on_device=1)
+        eng.stage(prim)
 
     # plain FP64 per-stage path on the same batch and first seed
     plain = None
@@ -237,6 +239,7 @@ def main():
     ap.add_argument("--fp64-batched", type=int, default=1)
     ap.add_argument("--cpu-events", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pcie", action="store_true", help="skip the host-buffer (PCIe-inclusive) transport")
     ap.add_argument("--out", default=None)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES (counter calibration) and exit")
