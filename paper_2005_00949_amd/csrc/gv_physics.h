@@ -61,72 +61,7 @@ __device__ __forceinline__ const R* tab_base(const TabView<R>& tv, int m, int ty
     return tv.rec + (size_t)(m * 3 + type) * tv.n * kCols;
 }
 
-// The record of one node holds up to four columns; a photon record uses the
-// first two.  Records are 16 (FP32) or 32 (FP64) bytes aligned.
-template <int NC> __device__ __forceinline__ void load_rec(const float* p, float y[4])
-{
-    if (NC == 2) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
-        y[0] = v.x;
-        y[1] = v.y;
-        y[2] = y[3] = 0.0f;
-    } else {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        y[0] = v.x;
-        y[1] = v.y;
-        y[2] = v.z;
-        y[3] = v.w;
-    }
-}
-template <int NC> __device__ __forceinline__ void load_rec(const double* p, double y[4])
-{
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    y[0] = a.x;
-    y[1] = a.y;
-    if (NC == 2) {
-        y[2] = y[3] = 0.0;
-    } else {
-        const double2 b = *reinterpret_cast<const double2*>(p + 2);
-        y[2] = b.x;
-        y[3] = b.y;
-    }
-}
-
-// Table values at energy T: bin i (as find_bin), weight w and the NC
-// interpolated columns (as lerp_col).  The node energies and both records of
-// the bin guessed from log10(T) are fetched together; only if the guess is off
-// (T within rounding of a node) is the bin fixed up and fetched again.
-template <class R> struct TabPoint {
-    int i;
-    R w;
-    R c[4];
-};
-template <int NC, class R>
-__device__ __forceinline__ void tab_point(const TabView<R>& tv, const R* base, R T, double log10_emin, double bpd,
-                                          TabPoint<R>& tp)
-{
-    int i = (int)m_floor((m_log10(T) - (R)log10_emin) * (R)bpd);
-    i = i < 0 ? 0 : (i > tv.n - 2 ? tv.n - 2 : i);
-    R e0 = tv.E[i], e1 = tv.E[i + 1];
-    R y0[4], y1[4];
-    load_rec<NC>(base + i * kCols, y0);
-    load_rec<NC>(base + (i + 1) * kCols, y1);
-    if (!(T >= e0 && T < e1)) {
-        while (i > 0 && T < tv.E[i]) --i;
-        while (i < tv.n - 2 && T >= tv.E[i + 1]) ++i;
-        e0 = tv.E[i];
-        e1 = tv.E[i + 1];
-        load_rec<NC>(base + i * kCols, y0);
-        load_rec<NC>(base + (i + 1) * kCols, y1);
-    }
-    tp.i = i;
-    tp.w = (T - e0) / (e1 - e0);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tp.c[c] = y0[c] + (y1[c] - y0[c]) * tp.w;
-}
-
 // inverse of the linearly interpolated range: the kinetic energy at range r
-// (bisection over all nodes; range_inverse_from finds the same bin from a hint)
 template <class R>
 __device__ inline R range_inverse(const TabView<R>& tv, const R* base, R r)
 {
@@ -136,49 +71,6 @@ __device__ inline R range_inverse(const TabView<R>& tv, const R* base, R r)
     if (r >= base[(n - 1) * kCols + 3]) {
         lo = n - 2;
     } else {
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (base[mid * kCols + 3] <= r) lo = mid;
-            else hi = mid;
-        }
-    }
-    const R r0 = base[lo * kCols + 3], r1 = base[(lo + 1) * kCols + 3];
-    return tv.E[lo] + (tv.E[lo + 1] - tv.E[lo]) * (r - r0) / (r1 - r0);
-}
-
-// The same inverse, with the bin searched from `hint` outwards (doubling
-// steps, then bisection inside the bracket).  The range is strictly
-// increasing, so the bin with R[lo] <= r < R[lo + 1] is unique and the result
-// equals range_inverse's; a hint near the answer (the pre-step energy's bin
-// for the range left after a step) needs a few loads instead of ~10.
-template <class R>
-__device__ inline R range_inverse_from(const TabView<R>& tv, const R* base, R r, int hint)
-{
-    const int n = tv.n;
-    if (r <= base[3]) return tv.E[0] * r / base[3];
-    int lo, hi;
-    if (r >= base[(n - 1) * kCols + 3]) {
-        lo = n - 2;
-    } else {
-        const int j = hint < 0 ? 0 : (hint > n - 2 ? n - 2 : hint);
-        int step = 1;
-        if (base[j * kCols + 3] <= r) {
-            lo = j;
-            hi = j + 1;
-            while (hi < n - 1 && base[hi * kCols + 3] <= r) {
-                lo = hi;
-                step *= 2;
-                hi = hi + step < n - 1 ? hi + step : n - 1;
-            }
-        } else {
-            hi = j;
-            lo = j - 1;
-            while (lo > 0 && base[lo * kCols + 3] > r) {
-                hi = lo;
-                step *= 2;
-                lo = lo - step > 0 ? lo - step : 0;
-            }
-        }
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (base[mid * kCols + 3] <= r) lo = mid;

@@ -62,8 +62,6 @@ template <class R> struct Limits {
     R range;
     R stot, sa;
     R usel;
-    R S;        // restricted stopping power at the pre-step energy (charged)
-    int bin;    // table bin of the pre-step energy
     int m;      // material of the pre-step volume (-1 vacuum)
 };
 
@@ -191,8 +189,6 @@ __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>
     L.range = (R)0;
     L.s_eloss = big_len<R>();
     L.usel = (R)0;
-    L.S = (R)0;
-    L.bin = 0;
     L.s_phys = big_len<R>();
     // vacuum has no process: its STEP block is never needed (the streams are
     // counter-based, so not drawing it changes no other number)
@@ -201,15 +197,13 @@ __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>
     L.usel = u53<R>(b0.w[2], b0.w[3]);
     {
         const R* base = tab_base(c.tv, m, t.type);
-        TabPoint<R> tp;
-        if (t.type == kGamma) tab_point<2>(c.tv, base, t.T, c.ph->log10_emin, c.ph->bpd, tp);
-        else tab_point<4>(c.tv, base, t.T, c.ph->log10_emin, c.ph->bpd, tp);
-        L.bin = tp.i;
-        L.sa = tp.c[0];
-        L.stot = L.sa + tp.c[1];
+        const int i = find_bin(c.tv, t.T, c.ph->log10_emin, c.ph->bpd);
+        const R w = (t.T - c.tv.E[i]) / (c.tv.E[i + 1] - c.tv.E[i]);
+        L.sa = lerp_col(c.tv, base, i, 0, w);
+        const R sb = lerp_col(c.tv, base, i, 1, w);
+        L.stot = L.sa + sb;
         if (t.type != kGamma) {
-            L.S = tp.c[2];
-            L.range = tp.c[3];
+            L.range = lerp_col(c.tv, base, i, 3, w);
             L.s_eloss = L.range <= (R)0.1 ? L.range : m_max((R)0.2 * L.range, (R)0.1);
         }
     }
@@ -321,12 +315,12 @@ __device__ inline bool stage_eloss(const Ctx<P>& c, Track<P>& t, const Limits<R>
     const R Tp = pr.T_pre;
     const R s = (R)pr.s;
     R dE;
-    // the pre-step energy is the one stage_limit looked up: its stopping
-    // power and bin are reused
     if (s < (R)0.01 * L.range) {
-        dE = L.S * s;
+        const int i = find_bin(c.tv, Tp, c.ph->log10_emin, c.ph->bpd);
+        const R w = (Tp - c.tv.E[i]) / (c.tv.E[i + 1] - c.tv.E[i]);
+        dE = lerp_col(c.tv, base, i, 2, w) * s;
     } else {
-        dE = Tp - range_inverse_from(c.tv, base, L.range - s, L.bin);
+        dE = Tp - range_inverse(c.tv, base, L.range - s);
     }
     const R rtrack = P::kMixed ? (R)c.ph->r_track_f[L.m][t.type == kPositron] : (R)c.ph->r_track[L.m][t.type == kPositron];
     bool stopped = false;
