@@ -117,7 +117,7 @@ def run_gpu(args):
     launches = 0
     alg_bytes = 0.0
     edep_first = None
-    per_ms = []
+    per_ms, tail_ms = [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
         eng.transport_staged(seed + k, edep.data_ptr())
@@ -128,15 +128,17 @@ def run_gpu(args):
         launches += st["kernel_launches"]
         alg_bytes += st["alg_bytes"]
         per_ms.append(st["transport_ms"])
+        tail_ms.append(st["tail_kernel_ms"])
         if k == 0:
             edep_first = edep.cpu().numpy()
             st0 = st
-        log(f"[bench] step {k}: {st['transport_ms']:.1f} ms, {st['total_steps']} steps")
+        log(f"[bench] step {k}: {st['transport_ms']:.1f} ms ({st['tail_kernel_ms']:.1f} ms in the tail), "
+            f"{st['total_steps']} steps")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
                alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
-               autotune_ms=tune_ms)
+               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms)
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
@@ -290,6 +292,8 @@ def main():
             "queue_order": "stable" if st0["queue_order"] else "arrival"},
         "primaries_per_s": res["primaries"] / res["elapsed"],
         "median_ms_per_transport": res["median_ms"],
+        "ms_per_transport": [round(x, 2) for x in res["per_ms"]],
+        "tail_ms_per_transport": [round(x, 2) for x in res["tail_ms"]],
         "autotune_ms": res["autotune_ms"],
         "pcie_inclusive": {"ms_per_transport": res["pcie_inclusive_ms"],
                            "steps_per_s": res["pcie_inclusive_steps_per_s"]},

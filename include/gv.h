@@ -175,6 +175,9 @@ typedef struct {
     int32_t tuned;                  /* 1: basket/occupancy/inner steps left at 0 were set by
                                        the autotuner, 0: defaults or caller's values */
     int32_t queue_order;
+    int32_t reserved;
+    double tail_kernel_ms;          /* part of kernel_ms spent after the population peaked and
+                                       fell below the tail threshold (batched driver) */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

@@ -74,7 +74,8 @@ class Stats(C.Structure):
                 ("driver", C.c_int32), ("precision", C.c_int32), ("basket", C.c_int32),
                 ("occupancy", C.c_int32), ("inner_steps", C.c_int32), ("graph_steps", C.c_int32),
                 ("capacity", C.c_int64), ("state_bytes", C.c_double), ("autotune_ms", C.c_double),
-                ("tuned", C.c_int32), ("queue_order", C.c_int32)]
+                ("tuned", C.c_int32), ("queue_order", C.c_int32), ("reserved", C.c_int32),
+                ("tail_kernel_ms", C.c_double)]
 
 
 class DebugIO(C.Structure):

@@ -680,6 +680,7 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
         HIPCHK(hipEventElapsedTime(&ms, L.ev0, L.ev1));
         const int K = tail ? tu.tail_K : tu.K;
         L.stats.kernel_ms += ms;
+        if (tail) L.stats.tail_kernel_ms += ms;
         L.stats.kernel_launches += K;
         L.stats.iterations += K;
         L.stats.graph_replays += 1;
@@ -803,8 +804,9 @@ int reset_run_buffers(int64_t n_events)
 // steps).  Trial transports of a sample of the staged batch (its first
 // events, at least 1024 primaries, about an eighth of the batch) are timed by
 // step-kernel time; coordinate search over inner steps, then basket, then
-// occupancy, from the defaults.  The choice is cached per precision, queue
-// order and batch-size class; the trials' deposits and counters are discarded.
+// occupancy, from the defaults; a candidate replaces the incumbent only if it
+// is at least 3 % faster.  The choice is cached per precision, queue order and
+// batch-size class; the trials' deposits and counters are discarded.
 template <class P> int tuned_choice(int64_t n_events, uint64_t seed, std::array<int, 3>& choice)
 {
     L.tuned = false;
@@ -865,7 +867,8 @@ template <class P> int tuned_choice(int64_t n_events, uint64_t seed, std::array<
             double r = 0.0;
             rc = trial(c, r);
             if (rc) return rc;
-            if (r > best_rate) {
+            // a candidate must beat the incumbent by 3 % (timing noise)
+            if (r > 1.03 * best_rate) {
                 best_rate = r;
                 best = c;
             }

@@ -49,3 +49,40 @@ def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(gv, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         gv.load()
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler gives
+    the header's struct (compiled here with gcc against include/gv.h)."""
+    import shutil
+    import subprocess
+
+    import paper_2005_00949_amd as gv
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    mirrors = {"gv_material": gv.Material, "gv_geometry": gv.Geometry, "gv_tables": gv.Tables,
+               "gv_config": gv.Config, "gv_stats_t": gv.Stats, "gv_trace_rec": None, "gv_debug_io": gv.DebugIO}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gv.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        if py is not None:
+            for fname, _ in py._fields_:
+                lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in mirrors.items():
+        if py is None:
+            assert got[(cname, "size")] == gv.TRACE_DTYPE.itemsize
+            continue
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
