@@ -56,6 +56,13 @@ enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1 };
  * identical in every run.  Results are the same in both: a track's random
  * numbers are keyed by (event, track id, step), never by its queue slot. */
 enum { GV_ORDER_ARRIVAL = 0, GV_ORDER_STABLE = 1 };
+/* Accumulation of deposits and of the energy ledger.  FLOAT: FP64 atomic
+ * adds, whose sums depend on arrival order in the last bits.  FIXED: each
+ * deposit is rounded once to a whole number of 2^-40 MeV and summed with
+ * integer atomics, so results are bit-identical for any basket size,
+ * occupancy, inner steps and queue order (the reproducibility requirement of
+ * Sec. 5.1 carried to the scores); converted to MeV on return. */
+enum { GV_DEPOSIT_FLOAT = 0, GV_DEPOSIT_FIXED = 1 };
 
 /* A material: density and elemental composition by mass fraction.  The
  * library derives electron density, radiation length (Tsai, unless X0_cm > 0),
@@ -143,7 +150,7 @@ typedef struct {
     void* hip_stream;               /* hipStream_t to run on; NULL = the library's own */
     int64_t trace_cap;              /* > 0: record up to this many step records (tests) */
     int32_t queue_order;            /* GV_ORDER_ARRIVAL (default) or GV_ORDER_STABLE; batched driver */
-    int32_t reserved;               /* must be 0 */
+    int32_t deposit_mode;           /* GV_DEPOSIT_FLOAT (default) or GV_DEPOSIT_FIXED */
 } gv_config;
 
 /* Counters of the last gv_transport. */

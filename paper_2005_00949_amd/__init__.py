@@ -20,6 +20,7 @@ DRIVER_PLAIN, DRIVER_BATCHED = 0, 1
 P64, PMIX = 0, 1
 FIELD_HELIX, FIELD_RK4 = 0, 1
 ORDER_ARRIVAL, ORDER_STABLE = 0, 1
+DEPOSIT_FLOAT, DEPOSIT_FIXED = 0, 1
 DBG_STEP, DBG_PHILOX, DBG_COMPACT, DBG_TABLE, DBG_GEOM = 0, 1, 2, 3, 4
 MAX_ELEM = 8
 PROC_NAMES = ["compton", "pair", "moller", "bhabha", "brems_em", "brems_ep", "annihilation", "null"]
@@ -59,7 +60,7 @@ class Config(C.Structure):
                 ("max_steps_per_track", C.c_int64), ("capacity", C.c_int64),
                 ("max_events_in_flight", C.c_int64), ("chord_tol_cm", C.c_double),
                 ("push_cm", C.c_double), ("rk_frac", C.c_double), ("hip_stream", C.c_void_p),
-                ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("reserved", C.c_int32)]
+                ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("deposit_mode", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -179,7 +180,7 @@ class Engine:
                            graph_steps=0, field_method=FIELD_HELIX, edep_on_device=0,
                            max_steps_per_track=1 << 20, capacity=0, max_events_in_flight=0,
                            chord_tol_cm=1e-3, push_cm=1e-7, rk_frac=0.05, hip_stream=None, trace_cap=0,
-                           queue_order=ORDER_ARRIVAL)
+                           queue_order=ORDER_ARRIVAL, deposit_mode=DEPOSIT_FLOAT)
         self.configure(**config)
 
     def configure(self, **kw):

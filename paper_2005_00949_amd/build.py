@@ -22,6 +22,10 @@ def hipcc() -> str:
 
 def flags(debug: bool = False):
     f = ["-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-O3",
+         # no implicit fused multiply-adds: every kernel rounds an expression
+         # the same way, so FP64 histories (and fixed-point scores) are
+         # bit-identical across drivers and kernel instantiations
+         "-ffp-contract=off",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # float division and square root to within a few ulp (double stays IEEE)

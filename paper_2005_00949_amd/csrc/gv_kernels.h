@@ -93,7 +93,23 @@ struct Sinks {
     gv_trace_rec* trace;
     unsigned long long* trace_n;
     long long trace_cap;
+    int fixed;                    // deposits and ledger held as unsigned 2^-40 MeV integers
 };
+
+// Fixed-point scoring: every deposit is rounded once to an integer number of
+// 2^-40 MeV and summed with integer atomics, so the sums do not depend on the
+// order in which the deposits arrive (basket size, occupancy, queue order).
+// 100 GeV in one cell is 1.1e17 units, far below 2^64.
+constexpr double kFixedScale = 0x1p40;
+__device__ __forceinline__ unsigned long long to_fixed(double e)
+{
+    return e > 0.0 ? __double2ull_rn(e * kFixedScale) : 0ull;
+}
+__device__ __forceinline__ void sink_add(const Sinks& S, double* p, double e)
+{
+    if (S.fixed) atomicAdd(reinterpret_cast<unsigned long long*>(p), to_fixed(e));
+    else unsafeAtomicAdd(p, e);
+}
 
 template <class P, class R = typename P::R>
 __device__ inline void trace_step(const Sinks& S, const Track<P>& before_key, int vol_pre, const Track<P>& after,
@@ -126,15 +142,15 @@ template <class R>
 __device__ __forceinline__ void account_rare(const Sinks& S, uint32_t ev, const StepOut<R>& o, unsigned* lds_cnt)
 {
     if (o.status == kEscaped) {
-        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 0], o.e_escaped);
+        sink_add(S, &S.ledger[(size_t)ev * 4 + 0], o.e_escaped);
         atomicAdd(&lds_cnt[kCEscaped], 1u);
     } else if (o.status == kKilled) {
-        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], o.e_killed);
+        sink_add(S, &S.ledger[(size_t)ev * 4 + 1], o.e_killed);
         atomicAdd(&lds_cnt[kCKilled], 1u);
     }
-    if (o.n_pair) unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 2], 1.0);
+    if (o.n_pair) sink_add(S, &S.ledger[(size_t)ev * 4 + 2], 1.0);
     if (o.n_annih) {
-        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 3], 1.0);
+        sink_add(S, &S.ledger[(size_t)ev * 4 + 3], 1.0);
         atomicAdd(&lds_cnt[kCProc + kAnnih], 1u);
     }
     if (o.proc >= 0) atomicAdd(&lds_cnt[kCProc + o.proc], 1u);
@@ -147,8 +163,8 @@ __device__ __forceinline__ void deposit(const Sinks& S, uint32_t ev, int vol, do
 {
     if (e == 0.0) return;
     const int cell = vol_cell(c_geom, vol);
-    if (cell >= 0) unsafeAtomicAdd(&S.edep[(size_t)ev * c_geom.n_cells + cell], e);
-    else unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], e);
+    if (cell >= 0) sink_add(S, &S.edep[(size_t)ev * c_geom.n_cells + cell], e);
+    else sink_add(S, &S.ledger[(size_t)ev * 4 + 1], e);
 }
 
 // Per-workgroup deposit cache (batched driver): an open-addressed table in LDS
@@ -173,12 +189,30 @@ template <int BLOCK> __device__ __forceinline__ void dep_clear(DepCache& dc)
     }
 }
 
-__device__ __forceinline__ void dep_add(DepCache& dc, const Sinks& S, uint32_t ev, int vol, double e)
+// A track's deposits over consecutive steps in one volume: a double sum, or
+// in fixed mode the sum of each step's rounded integer (so that the grouping
+// of steps into launches cannot change a single bit).
+struct DepAcc {
+    double e;
+    unsigned long long x;
+};
+__device__ __forceinline__ void acc_add(const Sinks& S, DepAcc& a, double e)
 {
-    if (e == 0.0) return;
+    if (S.fixed) a.x += to_fixed(e);
+    else a.e += e;
+}
+__device__ __forceinline__ void sink_add_acc(const Sinks& S, double* p, const DepAcc& a)
+{
+    if (S.fixed) atomicAdd(reinterpret_cast<unsigned long long*>(p), a.x);
+    else unsafeAtomicAdd(p, a.e);
+}
+
+__device__ __forceinline__ void dep_add(DepCache& dc, const Sinks& S, uint32_t ev, int vol, const DepAcc& a)
+{
+    if (a.e == 0.0 && a.x == 0ull) return;
     const int cell = vol_cell(c_geom, vol);
     if (cell < 0) {
-        unsafeAtomicAdd(&S.ledger[(size_t)ev * 4 + 1], e);
+        sink_add_acc(S, &S.ledger[(size_t)ev * 4 + 1], a);
         return;
     }
     const uint64_t k64 = (uint64_t)ev * (uint64_t)c_geom.n_cells + (uint64_t)cell;
@@ -189,14 +223,21 @@ __device__ __forceinline__ void dep_add(DepCache& dc, const Sinks& S, uint32_t e
             const uint32_t old = atomicCAS(&dc.key[h], kDepEmpty, k);
             if (old == kDepEmpty || old == k) {
                 // explicit LDS address space: the add must be a ds atomic
-                typedef __attribute__((address_space(3))) double lds_double;
-                __hip_atomic_fetch_add((lds_double*)&dc.val[h], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (S.fixed) {
+                    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+                    __hip_atomic_fetch_add((lds_u64*)&dc.val[h], a.x, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    typedef __attribute__((address_space(3))) double lds_double;
+                    __hip_atomic_fetch_add((lds_double*)&dc.val[h], a.e, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
                 return;
             }
             h = (h + 1) & (kDepSlots - 1);
         }
     }
-    unsafeAtomicAdd(&S.edep[k64], e);
+    sink_add_acc(S, &S.edep[k64], a);
 }
 
 // write the cached sums to HBM and empty the cache (all threads call it)
@@ -206,12 +247,25 @@ template <int BLOCK> __device__ __forceinline__ void dep_flush(DepCache& dc, con
     for (int i = threadIdx.x; i < kDepSlots; i += BLOCK) {
         const uint32_t k = dc.key[i];
         if (k != kDepEmpty) {
-            unsafeAtomicAdd(&S.edep[k], dc.val[i]);
+            if (S.fixed)   // the slot holds an integer sum
+                atomicAdd(reinterpret_cast<unsigned long long*>(&S.edep[k]),
+                          (unsigned long long)__double_as_longlong(dc.val[i]));
+            else
+                unsafeAtomicAdd(&S.edep[k], dc.val[i]);
             dc.key[i] = kDepEmpty;
             dc.val[i] = 0.0;
         }
     }
     __syncthreads();
+}
+
+// fixed-point sums (bit patterns in a double array) to MeV, in place
+__global__ void k_fixed_to_double(double* a, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long v = (unsigned long long)__double_as_longlong(a[i]);
+    a[i] = (double)v * (1.0 / kFixedScale);
 }
 
 // ===========================================================================
@@ -598,7 +652,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         load_track(A.in[TY], slot, TY, t);
         t.type = TY;
         loads += 1;
-        double acc = 0.0;
+        DepAcc acc{0.0, 0ull};
         int acc_vol = t.vol;
         for (int k = 0; k < inner; ++k) {
             const uint32_t ns = t.nstep;
@@ -606,10 +660,11 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             steps_here += o.did_step;
             if (o.vol_pre != acc_vol) {
                 dep_add(dc, A.S, t.ev, acc_vol, acc);
-                acc = 0.0;
+                acc.e = 0.0;
+                acc.x = 0ull;
                 acc_vol = o.vol_pre;
             }
-            acc += o.edep;
+            acc_add(A.S, acc, o.edep);
             if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
             account_rare(A.S, t.ev, o, cnt_lds);
             if (o.status != kAlive || o.nchild > 0) break;

@@ -129,13 +129,13 @@ struct GraphKey {
     const void* edep = nullptr;
     const void* trace = nullptr;
     long long trace_cap = 0;
-    int order = -1;
+    int order = -1, fixed = -1;
     int grid = 0, tail_grid = 0, tail_K = 0;
     bool operator==(const GraphKey& o) const
     {
         return prec == o.prec && block == o.block && chunks == o.chunks && inner_bulk == o.inner_bulk &&
                inner_tail == o.inner_tail && K == o.K && tail == o.tail && cap == o.cap && qblock == o.qblock &&
-               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order &&
+               edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order && fixed == o.fixed &&
                grid == o.grid && tail_grid == o.tail_grid && tail_K == o.tail_K;
     }
 };
@@ -224,7 +224,7 @@ gv_config default_config()
     c.hip_stream = nullptr;
     c.trace_cap = 0;
     c.queue_order = GV_ORDER_ARRIVAL;
-    c.reserved = 0;
+    c.deposit_mode = GV_DEPOSIT_FLOAT;
     return c;
 }
 
@@ -405,7 +405,8 @@ int validate_config(const gv_config& c)
     if (c.trace_cap < 0) return fail(GV_E_INVALID_ARG, "trace_cap");
     if (c.queue_order != GV_ORDER_ARRIVAL && c.queue_order != GV_ORDER_STABLE)
         return fail(GV_E_INVALID_ARG, "queue_order");
-    if (c.reserved != 0) return fail(GV_E_INVALID_ARG, "reserved field must be 0");
+    if (c.deposit_mode != GV_DEPOSIT_FLOAT && c.deposit_mode != GV_DEPOSIT_FIXED)
+        return fail(GV_E_INVALID_ARG, "deposit_mode");
     return GV_OK;
 }
 
@@ -506,6 +507,7 @@ Sinks make_sinks()
     S.trace = L.cfg.trace_cap > 0 ? L.trace.p : nullptr;
     S.trace_n = L.trace_n.p;
     S.trace_cap = L.cfg.trace_cap;
+    S.fixed = L.cfg.deposit_mode == GV_DEPOSIT_FIXED ? 1 : 0;
     return S;
 }
 
@@ -657,6 +659,7 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     key.trace = L.cfg.trace_cap > 0 ? L.trace.p : nullptr;
     key.trace_cap = L.cfg.trace_cap;
     key.order = L.cfg.queue_order;
+    key.fixed = L.cfg.deposit_mode;
     key.grid = tu.occupancy * L.n_cu;
     key.tail_grid = tu.tail_grid;
     key.tail_K = tu.tail_K;
@@ -1169,6 +1172,11 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     if (rc) return rc;
     // ---- results ----
     const size_t ne = (size_t)n_events * (size_t)L.n_cells;
+    if (L.cfg.deposit_mode == GV_DEPOSIT_FIXED) {
+        if (ne > 0) k_fixed_to_double<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(L.edep.p, (long long)ne);
+        k_fixed_to_double<<<(unsigned)((n_events * 4 + 255) / 256), 256, 0, s>>>(L.ledger.p, (long long)n_events * 4);
+        HIPCHK(hipGetLastError());
+    }
     if (L.n_cells > 0) {
         if (L.cfg.edep_on_device)
             HIPCHK(hipMemcpyAsync(edep_out, L.edep.p, ne * sizeof(double), hipMemcpyDeviceToDevice, s));

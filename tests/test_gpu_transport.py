@@ -231,3 +231,30 @@ def test_autotuner_choice_is_cached_and_exact(gv):
     scale = max(1.0, e3.max())
     assert np.allclose(e1, e3, rtol=1e-12, atol=1e-12 * scale)
     assert np.allclose(e2, e3, rtol=1e-12, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("prec", ["p64", "pmix"])
+def test_fixed_point_scores_bit_identical(gv, prec):
+    """Fixed-point scoring: deposits and ledgers are bit-identical for any
+    basket, occupancy, inner steps and queue order (and, in FP64, for the
+    plain driver too), and equal the FP64-atomic sums to rounding."""
+    geom, prim, seed = gv_inputs.workload("c4", 150)
+    p = gv.P64 if prec == "p64" else gv.PMIX
+    runs = []
+    for basket, occ, inner, order in [(256, 4, 4, gv.ORDER_ARRIVAL), (64, 1, 1, gv.ORDER_STABLE),
+                                      (512, 2, 2, gv.ORDER_ARRIVAL), (128, 8, 8, gv.ORDER_STABLE)]:
+        eng = gv.Engine(geom, precision=p, basket=basket, occupancy=occ, inner_steps=inner, queue_order=order,
+                        deposit_mode=gv.DEPOSIT_FIXED)
+        runs.append((eng.transport(prim, seed), eng.ledger(), eng.stats()["total_steps"]))
+    if prec == "p64":
+        eng = gv.Engine(geom, driver=gv.DRIVER_PLAIN, precision=gv.P64, deposit_mode=gv.DEPOSIT_FIXED)
+        runs.append((eng.transport(prim, seed), eng.ledger(), eng.stats()["total_steps"]))
+    for k, (e, led, n) in enumerate(runs[1:], 1):
+        print(f"\n[fixed {prec} run {k}] steps {n}, cells differing {int((e != runs[0][0]).sum())}, "
+              f"max |diff| {float(np.abs(e - runs[0][0]).max()):.3e}, ledger differing {int((led != runs[0][1]).sum())}")
+    for e, led, n in runs[1:]:
+        assert n == runs[0][2]
+        assert np.array_equal(e, runs[0][0])
+        assert np.array_equal(led, runs[0][1])
+    ef = gv.Engine(geom, precision=p).transport(prim, seed)
+    assert np.allclose(runs[0][0], ef, rtol=1e-9, atol=1e-9)
