@@ -45,7 +45,7 @@ class Config(C.Structure):
     _fields_ = [("e_min", C.c_double), ("bins_per_decade", C.c_double), ("n_nodes", C.c_int32),
                 ("field_method", C.c_int32), ("t_cut", C.c_double), ("k_cut", C.c_double),
                 ("t_track", C.c_double), ("chord_tol", C.c_double), ("push", C.c_double),
-                ("rk_frac", C.c_double), ("max_steps", C.c_int64)]
+                ("rk_frac", C.c_double), ("max_steps", C.c_int64), ("fs_alias", C.c_int32), ("pad", C.c_int32)]
 
 
 TRACE_DTYPE = np.dtype([("tid", "<u8"), ("event", "<u4"), ("nstep", "<u4"), ("type", "<i4"),
@@ -117,8 +117,19 @@ def load(rebuild: bool = False):
     lib.or_rotate.argtypes = [dp, C.c_double, C.c_double, C.c_double]
     for name in ["or_sample_compton", "or_sample_pair", "or_sample_brems", "or_sample_moller",
                  "or_sample_bhabha"]:
-        getattr(lib, name).argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, dp]
-        getattr(lib, name).restype = C.c_int
+        for nm in (name, name + "_alias"):
+            getattr(lib, nm).argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, dp]
+            getattr(lib, nm).restype = C.c_int
+    lib.or_alias_node_energy.argtypes = [C.c_int32]
+    lib.or_alias_node_energy.restype = C.c_double
+    lib.or_alias_table.argtypes = [C.c_int32, C.c_int32, dp, dp, ip]
+    lib.or_alias_table.restype = C.c_int32
+    lib.or_alias_pdf.argtypes = [C.c_int32, C.c_double, C.c_double]
+    lib.or_alias_pdf.restype = C.c_double
+    lib.or_alias_var.argtypes = [C.c_int32, C.c_double, C.c_double]
+    lib.or_alias_var.restype = C.c_double
+    lib.or_alias_xi.argtypes = [C.c_int32, C.c_double, dp]
+    lib.or_alias_xi.restype = C.c_double
     _lib = lib
     return lib
 
@@ -182,6 +193,7 @@ class Oracle:
         cfg.rk_frac = rs["rk_frac"]
         cfg.max_steps = rs["max_steps"]
         cfg.field_method = rs["field_method"]
+        cfg.fs_alias = rs.get("fs_alias", 0)
         rc = self.lib.or_setup(arr, len(mats), C.byref(g), C.byref(cfg))
         if rc != 0:
             raise RuntimeError("oracle setup failed: " + self.lib.or_error().decode())

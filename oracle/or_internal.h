@@ -35,6 +35,7 @@ typedef struct {
 extern or_ctx G;
 
 void or_set_error(const char* msg);
+void or_build_alias(void);
 void or_free_tables(void);
 int or_build_tables(void);
 int32_t or_vol_material(int32_t vol);

@@ -68,6 +68,7 @@ int or_setup(const or_material* mats, int32_t n_mats, const or_geometry* geom, c
         return -1;
     }
     or_setup_materials(mats, n_mats);
+    or_build_alias();
     G.axis = geom->axis;
     G.n_vol = geom->n_vol;
     if (G.n_vol <= 0) {
@@ -177,7 +178,8 @@ static void interact(uint64_t seed, uint32_t ev, trk_t* t, int first, step_t* si
         double k = t->T;
         if (first) {  /* Compton */
             si->proc = OR_PROC_COMPTON;
-            count_rej(or_sample_compton(k, seed, ev, t->tid, t->nstep, out), C);
+            count_rej((cf->fs_alias >> OR_AL_COMPTON) & 1 ? or_sample_compton_alias(k, seed, ev, t->tid, t->nstep, out)
+                                                         : or_sample_compton(k, seed, ev, t->tid, t->nstep, out), C);
             double k1 = out[0] * k, Te = k - k1;
             double u0[3] = {t->dir[0], t->dir[1], t->dir[2]};
             or_rotate(t->dir, out[1], sqrt(out[3]), out[2]);
@@ -205,7 +207,8 @@ static void interact(uint64_t seed, uint32_t ev, trk_t* t, int first, step_t* si
                 return;
             }
             si->proc = OR_PROC_PAIR;
-            count_rej(or_sample_pair(k, seed, ev, t->tid, t->nstep, out), C);
+            count_rej((cf->fs_alias >> OR_AL_PAIR) & 1 ? or_sample_pair_alias(k, seed, ev, t->tid, t->nstep, out)
+                                                      : or_sample_pair(k, seed, ev, t->tid, t->nstep, out), C);
             double Em = out[0] * k, Ep = (1.0 - out[0]) * k;
             double Tm = Em - OR_ME, Tp = Ep - OR_ME;
             double th_m = OR_ME / Em, th_p = OR_ME / Ep;
@@ -231,8 +234,10 @@ static void interact(uint64_t seed, uint32_t ev, trk_t* t, int first, step_t* si
                 return;
             }
             si->proc = pos ? OR_PROC_BHABHA : OR_PROC_MOLLER;
-            if (pos) count_rej(or_sample_bhabha(T, seed, ev, t->tid, t->nstep, out), C);
-            else count_rej(or_sample_moller(T, seed, ev, t->tid, t->nstep, out), C);
+            if (pos) count_rej((cf->fs_alias >> OR_AL_BHABHA) & 1 ? or_sample_bhabha_alias(T, seed, ev, t->tid, t->nstep, out)
+                                                                : or_sample_bhabha(T, seed, ev, t->tid, t->nstep, out), C);
+            else count_rej((cf->fs_alias >> OR_AL_MOLLER) & 1 ? or_sample_moller_alias(T, seed, ev, t->tid, t->nstep, out)
+                                                            : or_sample_moller(T, seed, ev, t->tid, t->nstep, out), C);
             double Td = out[0] * T;
             double cost = sqrt(Td * (T + 2.0 * OR_ME) / (T * (Td + 2.0 * OR_ME)));
             double sint = sqrt(2.0 * OR_ME * (T - Td) / (T * (Td + 2.0 * OR_ME)));
@@ -257,7 +262,8 @@ static void interact(uint64_t seed, uint32_t ev, trk_t* t, int first, step_t* si
                 return;
             }
             si->proc = (t->type == OR_POSITRON) ? OR_PROC_BREMS_EP : OR_PROC_BREMS_EM;
-            count_rej(or_sample_brems(T, seed, ev, t->tid, t->nstep, out), C);
+            count_rej((cf->fs_alias >> OR_AL_BREMS) & 1 ? or_sample_brems_alias(T, seed, ev, t->tid, t->nstep, out)
+                                                       : or_sample_brems(T, seed, ev, t->tid, t->nstep, out), C);
             double k = out[0];
             child_ids(seed, ev, t, ids);
             make_child(si, 0, ids, OR_GAMMA, k, t->dir, t);

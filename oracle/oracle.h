@@ -76,7 +76,17 @@ typedef struct {
     double push;                    /* field: push past a boundary */
     double rk_frac;                 /* RK4 substep as a fraction of the radius */
     int64_t max_steps;              /* looper cap */
+    int32_t fs_alias;               /* bit m set: model m samples from tables (OR_AL_*) */
+    int32_t pad;
 } or_config;
+
+/* Final-state models with a table (alias) sampler; bit m of fs_alias */
+enum { OR_AL_COMPTON = 0, OR_AL_PAIR = 1, OR_AL_BREMS = 2, OR_AL_MOLLER = 3, OR_AL_BHABHA = 4,
+       OR_AL_NMOD = 5 };
+#define OR_AL_NX 64       /* sub-intervals of the transformed variable per node */
+#define OR_AL_NPD 20      /* primary-energy nodes per decade */
+#define OR_AL_NE 121      /* nodes 0.1 MeV .. 100 GeV */
+#define OR_AL_E0 0.1
 
 typedef struct {
     int32_t pdg;
@@ -138,6 +148,19 @@ int or_single_step(int64_t n, uint64_t seed,
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_u53(uint32_t wa, uint32_t wb);
 double or_u32(uint32_t w);
+
+/* table sampling: node energies, the tables of one node, one sample of the
+ * transformed variable from four uniforms, and the samplers themselves */
+double or_alias_node_energy(int32_t j);
+int32_t or_alias_table(int32_t model, int32_t j, double* p, double* q, int32_t* alias);
+double or_alias_pdf(int32_t model, double E, double xi);
+double or_alias_var(int32_t model, double E, double xi);
+double or_alias_xi(int32_t model, double E, const double u[4]);
+int or_sample_compton_alias(double k, uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, double out[4]);
+int or_sample_pair_alias(double k, uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, double out[4]);
+int or_sample_brems_alias(double T, uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, double out[4]);
+int or_sample_moller_alias(double T, uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, double out[4]);
+int or_sample_bhabha_alias(double T, uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, double out[4]);
 double or_expo(uint32_t wa, uint32_t wb);
 void or_stream(uint64_t seed, uint32_t event, uint64_t tid, uint32_t nstep, uint32_t purpose,
                uint32_t out[4]);
