@@ -152,6 +152,29 @@ def run_gpu(args):
         eng.configure(edep_on_device=1)
         eng.stage(prim)
 
+    # the same batch with every final state sampled from the alias tables
+    # (the second sampling method of the paper's physics library)
+    tables = None
+    if args.table_steps > 0:
+        eng.configure(fs_alias=gv.FS_ALL)
+        eng.transport_staged(seed, edep.data_ptr())          # warm-up (graph capture)
+        edep_tab = edep.cpu().numpy()
+        tt, ttail, tsteps = [], [], 0
+        for k in range(args.table_steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.transport_staged(seed + k, edep.data_ptr())
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t)
+            st = eng.stats()
+            tsteps += st["total_steps"]
+            ttail.append(round(st["tail_kernel_ms"], 2))
+        tables = dict(steps_per_s=tsteps / sum(tt), median_ms_per_transport=float(np.median(tt)) * 1e3,
+                      ms_per_transport=[round(x * 1e3, 2) for x in tt], tail_ms_per_transport=ttail,
+                      edep_vs_rejection=paired_layers(edep_tab, edep_first))
+        log(f"[bench] table sampling: {tables['steps_per_s']:.3g} steps/s")
+        eng.configure(fs_alias=0)
+
     # plain FP64 per-stage path on the same batch and first seed
     plain = None
     if args.plain_steps > 0:
@@ -190,6 +213,7 @@ def run_gpu(args):
         st = eng.stats()
         b64 = dict(steps_per_s=st["total_steps"] / dt, primaries_per_s=len(prim) / dt, ms_per_transport=dt * 1e3)
         log(f"[bench] batched FP64: {dt*1e3:.1f} ms")
+    res["tables"] = tables
     return res, plain, b64
 
 
@@ -238,6 +262,8 @@ def main():
     ap.add_argument("--occupancy", type=int, default=0)
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--table-steps", type=int, default=3,
+                    help="timed transports with table (alias) final-state sampling")
     ap.add_argument("--fp64-batched", type=int, default=1)
     ap.add_argument("--cpu-events", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
@@ -301,6 +327,7 @@ def main():
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (value / plain["steps_per_s"]) if plain else None,
         "batched_fp64": b64,
+        "table_sampling": res["tables"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),

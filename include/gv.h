@@ -63,6 +63,14 @@ enum { GV_ORDER_ARRIVAL = 0, GV_ORDER_STABLE = 1 };
  * occupancy, inner steps and queue order (the reproducibility requirement of
  * Sec. 5.1 carried to the scores); converted to MeV on return. */
 enum { GV_DEPOSIT_FLOAT = 0, GV_DEPOSIT_FIXED = 1 };
+/* Final-state models that can sample from tables instead of by
+ * composition-rejection (the two sampling methods of Sec. 3.5).  Table
+ * sampling: a discrete variable picks one of the two primary-energy nodes
+ * around E (20 per decade, 0.1 MeV - 100 GeV) with the linear weight in
+ * ln E; Walker's alias table of that node picks one of 64 sub-intervals of a
+ * transformed variable, inside which the tabulated linear density is sampled
+ * exactly: four uniforms and no loop.  Bit m of gv_config.fs_alias. */
+enum { GV_FS_COMPTON = 0, GV_FS_PAIR = 1, GV_FS_BREMS = 2, GV_FS_MOLLER = 3, GV_FS_BHABHA = 4 };
 
 /* A material: density and elemental composition by mass fraction.  The
  * library derives electron density, radiation length (Tsai, unless X0_cm > 0),
@@ -151,6 +159,9 @@ typedef struct {
     int64_t trace_cap;              /* > 0: record up to this many step records (tests) */
     int32_t queue_order;            /* GV_ORDER_ARRIVAL (default) or GV_ORDER_STABLE; batched driver */
     int32_t deposit_mode;           /* GV_DEPOSIT_FLOAT (default) or GV_DEPOSIT_FIXED */
+    int32_t fs_alias;               /* bit m set (m = GV_FS_*): model m samples its final state
+                                       from tables instead of by rejection; default 0 */
+    int32_t reserved2;              /* must be 0 */
 } gv_config;
 
 /* Counters of the last gv_transport. */
@@ -235,6 +246,13 @@ int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out);
 
 /* Number of scoring cells of the current geometry. */
 int gv_n_cells(int32_t* out);
+
+/* Test access to the final-state table of one model (GV_FS_*) at one node
+ * (0..120, energy 0.1 MeV * 10^(node/20)): the density at 65 points (p), the
+ * 64 alias thresholds (q) and alias columns, and whether the node lies above
+ * the model's threshold.  Caller-owned outputs.  GV_E_NOT_INIT,
+ * GV_E_INVALID_ARG. */
+int gv_alias_table(int32_t model, int32_t node, double* p, double* q, int32_t* alias, int32_t* valid);
 
 /* Release device memory; the context must be re-initialised to be used. */
 void gv_finalize(void);

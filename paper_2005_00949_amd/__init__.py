@@ -21,6 +21,8 @@ P64, PMIX = 0, 1
 FIELD_HELIX, FIELD_RK4 = 0, 1
 ORDER_ARRIVAL, ORDER_STABLE = 0, 1
 DEPOSIT_FLOAT, DEPOSIT_FIXED = 0, 1
+FS_COMPTON, FS_PAIR, FS_BREMS, FS_MOLLER, FS_BHABHA = 0, 1, 2, 3, 4
+FS_ALL = 31
 DBG_STEP, DBG_PHILOX, DBG_COMPACT, DBG_TABLE, DBG_GEOM = 0, 1, 2, 3, 4
 MAX_ELEM = 8
 PROC_NAMES = ["compton", "pair", "moller", "bhabha", "brems_em", "brems_ep", "annihilation", "null"]
@@ -60,7 +62,8 @@ class Config(C.Structure):
                 ("max_steps_per_track", C.c_int64), ("capacity", C.c_int64),
                 ("max_events_in_flight", C.c_int64), ("chord_tol_cm", C.c_double),
                 ("push_cm", C.c_double), ("rk_frac", C.c_double), ("hip_stream", C.c_void_p),
-                ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("deposit_mode", C.c_int32)]
+                ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("deposit_mode", C.c_int32),
+                ("fs_alias", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -119,6 +122,7 @@ def load():
     lib.gv_n_cells.argtypes = [C.POINTER(C.c_int32)]
     lib.gv_finalize.restype = None
     lib.gv_debug_step.argtypes = [C.c_int32, C.c_int64, C.POINTER(DebugIO)]
+    lib.gv_alias_table.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     _lib = lib
     return lib
 
@@ -180,7 +184,7 @@ class Engine:
                            graph_steps=0, field_method=FIELD_HELIX, edep_on_device=0,
                            max_steps_per_track=1 << 20, capacity=0, max_events_in_flight=0,
                            chord_tol_cm=1e-3, push_cm=1e-7, rk_frac=0.05, hip_stream=None, trace_cap=0,
-                           queue_order=ORDER_ARRIVAL, deposit_mode=DEPOSIT_FLOAT)
+                           queue_order=ORDER_ARRIVAL, deposit_mode=DEPOSIT_FLOAT, fs_alias=0)
         self.configure(**config)
 
     def configure(self, **kw):
@@ -317,6 +321,13 @@ class Engine:
         io.d_bnd, io.vol, io.vol_pre, io.safety = _p(out["d_bnd"]), _p(out["next"]), _p(out["vol"]), _p(out["safety"])
         self._debug(DBG_GEOM, n, io)
         return out
+
+    def alias_table(self, model, node):
+        """Final-state table of one model at one node: (valid, p, q, alias)."""
+        p, q = np.zeros(65), np.zeros(64)
+        a, v = np.zeros(64, dtype=np.int32), np.zeros(1, dtype=np.int32)
+        _check(self.lib.gv_alias_table(model, node, p.ctypes.data, q.ctypes.data, a.ctypes.data, v.ctypes.data))
+        return bool(v[0]), p, q, a
 
     def close(self):
         self.lib.gv_finalize()

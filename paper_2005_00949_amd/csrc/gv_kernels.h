@@ -259,6 +259,62 @@ template <int BLOCK> __device__ __forceinline__ void dep_flush(DepCache& dc, con
     __syncthreads();
 }
 
+// Final-state tables, one thread per (model, node): node energy, the density
+// of the transformed variable at kAlNX + 1 points, and Walker's alias table of
+// the sub-interval trapezoid weights (Vose's construction: scaled weights
+// below 1 and at or above 1 on two stacks filled in increasing index order; the
+// top small column keeps its share and hands the rest to the top large one).
+__global__ void k_build_alias(double* rec, int* alias, double* E, int* valid, double tc, double kc)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kAlNMod * kAlNE) return;
+    const int m = idx / kAlNE, j = idx % kAlNE;
+    const double En = kAlE0 * pow(10.0, (double)j / kAlNPD);
+    if (m == 0) E[j] = En;
+    double* r = rec + (size_t)idx * kAlRec;
+    int* a = alias + (size_t)idx * kAlNX;
+    const bool ok = alias_model_valid(m, En, tc, kc);
+    valid[idx] = ok ? 1 : 0;
+    if (!ok) {
+        for (int k = 0; k < kAlRec; ++k) r[k] = 0.0;
+        for (int k = 0; k < kAlNX; ++k) a[k] = k;
+        return;
+    }
+    for (int k = 0; k <= kAlNX; ++k) r[k] = alias_pdf(m, En, (double)k / kAlNX, tc, kc);
+    double sc[kAlNX];
+    int small[kAlNX], large[kAlNX];
+    int ns = 0, nl = 0;
+    double sum = 0.0;
+    for (int k = 0; k < kAlNX; ++k) {
+        sc[k] = 0.5 * (r[k] + r[k + 1]);
+        sum += sc[k];
+    }
+    for (int k = 0; k < kAlNX; ++k) {
+        sc[k] = (double)kAlNX * sc[k] / sum;
+        if (sc[k] < 1.0) small[ns++] = k;
+        else large[nl++] = k;
+    }
+    double* q = r + kAlNX + 1;
+    while (ns > 0 && nl > 0) {
+        const int lo = small[--ns], hi = large[--nl];
+        q[lo] = sc[lo];
+        a[lo] = hi;
+        sc[hi] = (sc[hi] + sc[lo]) - 1.0;
+        if (sc[hi] < 1.0) small[ns++] = hi;
+        else large[nl++] = hi;
+    }
+    while (nl > 0) {
+        const int k = large[--nl];
+        q[k] = 1.0;
+        a[k] = k;
+    }
+    while (ns > 0) {
+        const int k = small[--ns];
+        q[k] = 1.0;
+        a[k] = k;
+    }
+}
+
 // fixed-point sums (bit patterns in a double array) to MeV, in place
 __global__ void k_fixed_to_double(double* a, long long n)
 {

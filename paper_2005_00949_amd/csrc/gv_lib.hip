@@ -152,6 +152,9 @@ struct Lib {
     int n_cells = 0;
     // tables
     DBuf<double> rec64, E64;
+    DBuf<double> al_rec64, al_E64;   // final-state tables (alias sampling)
+    DBuf<float> al_rec32, al_E32;
+    DBuf<int> al_alias, al_valid;
     DBuf<float> rec32, E32;
     // transport state
     QueueMem<P64> q64;
@@ -225,6 +228,8 @@ gv_config default_config()
     c.trace_cap = 0;
     c.queue_order = GV_ORDER_ARRIVAL;
     c.deposit_mode = GV_DEPOSIT_FLOAT;
+    c.fs_alias = 0;
+    c.reserved2 = 0;
     return c;
 }
 
@@ -250,6 +255,12 @@ void release_all()
     L.E64.release();
     L.rec32.release();
     L.E32.release();
+    L.al_rec64.release();
+    L.al_rec32.release();
+    L.al_E64.release();
+    L.al_E32.release();
+    L.al_alias.release();
+    L.al_valid.release();
     L.q64.release();
     L.qmix.release();
     L.plain_pool.release();
@@ -374,6 +385,33 @@ int build_tables()
             L.phys.r_track[m][p] = hr64[2 * m + p];
             L.phys.r_track_f[m][p] = hr32[2 * m + p];
         }
+    // final-state tables for alias sampling (independent of material)
+    const size_t arec = (size_t)kAlNMod * kAlNE * kAlRec;
+    HIPCHK(L.al_rec64.ensure(arec));
+    HIPCHK(L.al_rec32.ensure(arec));
+    HIPCHK(L.al_E64.ensure(kAlNE));
+    HIPCHK(L.al_E32.ensure(kAlNE));
+    HIPCHK(L.al_alias.ensure((size_t)kAlNMod * kAlNE * kAlNX));
+    HIPCHK(L.al_valid.ensure((size_t)kAlNMod * kAlNE));
+    k_build_alias<<<(kAlNMod * kAlNE + 63) / 64, 64, 0, s>>>(L.al_rec64.p, L.al_alias.p, L.al_E64.p, L.al_valid.p,
+                                                             L.phys.t_cut, L.phys.k_cut);
+    HIPCHK(hipGetLastError());
+    k_to_float<<<(unsigned)((arec + 255) / 256), 256, 0, s>>>(L.al_rec64.p, L.al_rec32.p, arec);
+    k_to_float<<<1, 256, 0, s>>>(L.al_E64.p, L.al_E32.p, (size_t)kAlNE);
+    HIPCHK(hipGetLastError());
+    {
+        std::vector<double> ha(arec);
+        HIPCHK(hipMemcpyAsync(ha.data(), L.al_rec64.p, arec * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (double v : ha)
+            if (!std::isfinite(v) || v < 0.0) return fail(GV_E_TABLES, "invalid final-state table value");
+    }
+    L.phys.al_rec64 = L.al_rec64.p;
+    L.phys.al_rec32 = L.al_rec32.p;
+    L.phys.al_E64 = L.al_E64.p;
+    L.phys.al_E32 = L.al_E32.p;
+    L.phys.al_alias = L.al_alias.p;
+    L.phys.al_valid = L.al_valid.p;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_phys), &L.phys, sizeof(DevPhys), 0, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return GV_OK;
@@ -407,6 +445,8 @@ int validate_config(const gv_config& c)
         return fail(GV_E_INVALID_ARG, "queue_order");
     if (c.deposit_mode != GV_DEPOSIT_FLOAT && c.deposit_mode != GV_DEPOSIT_FIXED)
         return fail(GV_E_INVALID_ARG, "deposit_mode");
+    if (c.fs_alias < 0 || c.fs_alias >= (1 << kAlNMod)) return fail(GV_E_INVALID_ARG, "fs_alias");
+    if (c.reserved2 != 0) return fail(GV_E_INVALID_ARG, "reserved field must be 0");
     return GV_OK;
 }
 
@@ -417,6 +457,7 @@ int apply_run_params()
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
     L.phys.max_steps = L.cfg.max_steps_per_track;
+    L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_phys), &L.phys, sizeof(DevPhys), 0, hipMemcpyHostToDevice, stream()));
     HIPCHK(hipStreamSynchronize(stream()));
     return GV_OK;
@@ -1056,6 +1097,7 @@ int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom, co
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
     L.phys.max_steps = L.cfg.max_steps_per_track;
+    L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_geom), &L.geom, sizeof(DevGeom), 0, hipMemcpyHostToDevice, stream()));
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_phys), &L.phys, sizeof(DevPhys), 0, hipMemcpyHostToDevice, stream()));
     int rc = build_tables();
@@ -1281,6 +1323,23 @@ int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out)
     const int64_t n = std::min<int64_t>(cap, L.stats.trace_records);
     if (n > 0) HIPCHK(hipMemcpy(out, L.trace.p, (size_t)n * sizeof(gv_trace_rec), hipMemcpyDeviceToHost));
     *n_out = n;
+    return GV_OK;
+}
+
+int gv_alias_table(int32_t model, int32_t node, double* p, double* q, int32_t* alias, int32_t* valid)
+{
+    if (!L.ready) return fail(GV_E_NOT_INIT, "gv_init has not succeeded");
+    if (model < 0 || model >= kAlNMod || node < 0 || node >= kAlNE || !p || !q || !alias || !valid)
+        return fail(GV_E_INVALID_ARG, "model/node out of range or null output");
+    const size_t idx = (size_t)model * kAlNE + node;
+    double rec[kAlRec];
+    hipStream_t s = stream();
+    HIPCHK(hipMemcpyAsync(rec, L.al_rec64.p + idx * kAlRec, sizeof(rec), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(alias, L.al_alias.p + idx * kAlNX, kAlNX * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(valid, L.al_valid.p + idx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k <= kAlNX; ++k) p[k] = rec[k];
+    for (int k = 0; k < kAlNX; ++k) q[k] = rec[kAlNX + 1 + k];
     return GV_OK;
 }
 

@@ -24,6 +24,16 @@ struct DevPhys {
     double t_cut, k_cut, t_track;
     double chord_tol, push, rk_frac;
     long long max_steps;
+    // final-state tables (alias sampling): model m uses them when bit m of
+    // fs_alias is set; records per (model, node) as built by k_build_alias
+    int fs_alias;
+    int pad2;
+    const double* al_rec64;
+    const float* al_rec32;
+    const double* al_E64;
+    const float* al_E32;
+    const int* al_alias;
+    const int* al_valid;
     DevMat mat[16];
     double r_track[16][2];   // range at the tracking cut, per material, e-/e+
     float r_track_f[16][2];
@@ -333,6 +343,148 @@ template <class R> __device__ inline bool sample_bhabha(R T, R tc, const Key& ke
         if (f.u[1] * ib2 <= val) return true;
     }
     return false;
+}
+
+// ---------------------------------------------------------------------------
+// Final states from tables (the sampling tables of Sec. 3.5): a discrete
+// variable picks the lower or upper of the two primary-energy nodes around E
+// (probability of the upper = the linear weight in ln E); Walker's alias
+// table of that node picks one of kAlNX sub-intervals of a transformed
+// variable xi in [0, 1]; inside it xi follows the tabulated linear density
+// exactly.  No loop, a fixed four uniforms (block FS0) plus the azimuth
+// (block FS0 + 1).  Transformed variables and their densities:
+//   Compton  eps = eps0^xi                 p ~ 1 + eps^2 - eps sin^2(theta)
+//   pair     x = a + xi (1 - 2a), a = m/k  p ~ 1 - 4/3 x (1 - x)
+//   brems    k = kc (T / kc)^xi            p ~ 1 - y + 3/4 y^2, y = k / E
+//   Moller   eps = ec (1 / (2 ec))^xi      p ~ eps dsigma/deps
+//   Bhabha   eps = ec (1 / ec)^xi          p ~ eps dsigma/deps
+// ---------------------------------------------------------------------------
+constexpr int kAlNX = 64;          // sub-intervals per node
+constexpr int kAlNPD = 20;         // nodes per decade of primary energy
+constexpr int kAlNE = 121;         // 0.1 MeV .. 100 GeV
+constexpr int kAlNMod = 5;
+constexpr int kAlRec = 2 * kAlNX + 1;   // record: density at kAlNX + 1 points, kAlNX alias thresholds
+constexpr double kAlE0 = 0.1;
+enum { kAlCompton = 0, kAlPair = 1, kAlBrems = 2, kAlMoller = 3, kAlBhabha = 4 };
+
+__host__ __device__ inline bool alias_model_valid(int m, double E, double tc, double kc)
+{
+    return m == kAlPair ? E > 2.0 * kMe : m == kAlBrems ? E > kc : m == kAlMoller ? E > 2.0 * tc
+                                        : m == kAlBhabha ? E > tc : E > 0.0;
+}
+
+// the sampled quantity at primary energy E for transformed variable xi
+template <class R> __device__ inline R alias_var(int m, R E, R xi, R tc, R kc)
+{
+    if (m == kAlCompton) return m_exp(xi * m_log((R)1 / ((R)1 + (R)2 * (E / (R)kMe))));
+    if (m == kAlPair) {
+        const R a = (R)kMe / E;
+        return a + xi * ((R)1 - (R)2 * a);
+    }
+    if (m == kAlBrems) return kc * m_exp(xi * m_log(E / kc));
+    const R ec = tc / E;
+    if (m == kAlMoller) return ec * m_exp(xi * m_log((R)0.5 / ec));
+    return ec * m_exp(xi * m_log((R)1 / ec));
+}
+
+// density of xi (unnormalised), for the table builder (double)
+__device__ inline double alias_pdf(int m, double E, double xi, double tc, double kc)
+{
+    const double v = alias_var<double>(m, E, xi, tc, kc);
+    if (m == kAlCompton) {
+        const double kk = E / kMe;
+        const double t = (1.0 - v) / (kk * v);
+        const double sin2 = t * (2.0 - t);
+        return 1.0 + v * v - v * sin2;
+    }
+    if (m == kAlPair) return 1.0 - (4.0 / 3.0) * v * (1.0 - v);
+    if (m == kAlBrems) {
+        const double y = v / (E + kMe);
+        return 1.0 - y + 0.75 * y * y;
+    }
+    const double g = (E + kMe) / kMe;
+    if (m == kAlMoller) {
+        const double g1 = ((g - 1.0) / g) * ((g - 1.0) / g);
+        const double g2 = (2.0 * g - 1.0) / (g * g);
+        return (g1 * v * v + 1.0 + v * v / ((1.0 - v) * (1.0 - v)) - g2 * v / (1.0 - v)) / v;
+    }
+    const double b2 = 1.0 - 1.0 / (g * g);
+    const double y = 1.0 / (g + 1.0);
+    const double B1 = 2.0 - y * y;
+    const double B2 = (1.0 - 2.0 * y) * (3.0 + y * y);
+    const double B4 = (1.0 - 2.0 * y) * (1.0 - 2.0 * y) * (1.0 - 2.0 * y);
+    const double B3 = B4 + (1.0 - 2.0 * y) * (1.0 - 2.0 * y);
+    return (1.0 / b2 - B1 * v + B2 * v * v - B3 * v * v * v + B4 * v * v * v * v) / v;
+}
+
+template <class R> struct AliasView {
+    const R* rec;
+    const R* E;
+    const int* alias;
+    const int* valid;
+};
+template <class R> __device__ __forceinline__ AliasView<R> alias_view(const DevPhys& ph);
+template <> __device__ __forceinline__ AliasView<double> alias_view<double>(const DevPhys& ph)
+{
+    return AliasView<double>{ph.al_rec64, ph.al_E64, ph.al_alias, ph.al_valid};
+}
+template <> __device__ __forceinline__ AliasView<float> alias_view<float>(const DevPhys& ph)
+{
+    return AliasView<float>{ph.al_rec32, ph.al_E32, ph.al_alias, ph.al_valid};
+}
+
+// one sample of xi for model m at energy E (valid for the model) from u[0..3]
+template <class R> __device__ inline R alias_xi(const AliasView<R>& av, int m, R E, const R u[4])
+{
+    int j = (int)m_floor(m_log10(E / (R)kAlE0) * (R)kAlNPD);
+    j = j < 0 ? 0 : (j > kAlNE - 2 ? kAlNE - 2 : j);
+    while (j > 0 && E < av.E[j]) --j;
+    while (j < kAlNE - 2 && E >= av.E[j + 1]) ++j;
+    const R lam = m_log(E / av.E[j]) / m_log(av.E[j + 1] / av.E[j]);
+    int jj = u[0] < lam ? j + 1 : j;
+    if (!av.valid[m * kAlNE + jj]) jj = j + 1;
+    const int node = m * kAlNE + jj;
+    const R* rec = av.rec + (size_t)node * kAlRec;
+    int k = (int)(u[1] * (R)kAlNX);
+    k = k > kAlNX - 1 ? kAlNX - 1 : k;
+    if (u[2] > rec[kAlNX + 1 + k]) k = av.alias[node * kAlNX + k];
+    const R a = rec[k], b = rec[k + 1];
+    R tau = u[3];
+    if (a + b > (R)0) tau = u[3] * (a + b) / (a + m_sqrt(a * a + (b * b - a * a) * u[3]));
+    tau = tau > (R)1 ? (R)1 : tau;
+    return ((R)k + tau) / (R)kAlNX;
+}
+
+// the four table uniforms and the azimuth
+template <class R> __device__ __forceinline__ R alias_uniforms(const Key& key, R u[4])
+{
+    const FS4<R> f = fs_uniforms<R>(key, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = f.u[i];
+    return (R)(2.0 * kPi) * fs_uniforms<R>(key, 1).u[0];
+}
+
+// Compton from the table: eps, om = 1 - eps (from expm1, no cancellation),
+// t = 1 - cos(theta), phi
+template <class R>
+__device__ inline void alias_compton(const AliasView<R>& av, R kMeV, const Key& key, R& eps, R& om, R& t, R& phi)
+{
+    R u[4];
+    phi = alias_uniforms<R>(key, u);
+    const R k = kMeV / (R)kMe;
+    const R lg = m_log((R)1 / ((R)1 + (R)2 * k));
+    const R xi = alias_xi<R>(av, kAlCompton, kMeV, u);
+    eps = m_exp(xi * lg);
+    om = -m_expm1(xi * lg);
+    t = om / (k * eps);
+}
+
+// pair, bremsstrahlung, Moller and Bhabha from their tables
+template <class R> __device__ inline R alias_sample(const AliasView<R>& av, int m, R E, R tc, R kc, const Key& key, R& phi)
+{
+    R u[4];
+    phi = alias_uniforms<R>(key, u);
+    return alias_var<R>(m, E, alias_xi<R>(av, m, E, u), tc, kc);
 }
 
 // ---------------------------------------------------------------------------

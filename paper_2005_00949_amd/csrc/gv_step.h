@@ -345,7 +345,10 @@ __device__ inline void interact(const Ctx<P>& c, Track<P>& t, bool first, StepOu
         if (first) {
             o.proc = kCompton;
             R eps, om, tt, phi;
-            if (!sample_compton<R>(k, key, eps, om, tt, phi)) o.rej_exhausted += 1;
+            if ((ph.fs_alias >> kAlCompton) & 1)
+                alias_compton<R>(alias_view<R>(ph), k, key, eps, om, tt, phi);
+            else if (!sample_compton<R>(k, key, eps, om, tt, phi))
+                o.rej_exhausted += 1;
             const R k1 = eps * k, Te = om * k;
             const R st = m_sqrt(tt * ((R)2 - tt));
             R de[3] = {t.u[0], t.u[1], t.u[2]};
@@ -375,7 +378,10 @@ __device__ inline void interact(const Ctx<P>& c, Track<P>& t, bool first, StepOu
             }
             o.proc = kPair;
             R x, phi;
-            if (!sample_pair<R>(k, key, x, phi)) o.rej_exhausted += 1;
+            if ((ph.fs_alias >> kAlPair) & 1)
+                x = alias_sample<R>(alias_view<R>(ph), kAlPair, k, (R)ph.t_cut, (R)ph.k_cut, key, phi);
+            else if (!sample_pair<R>(k, key, x, phi))
+                o.rej_exhausted += 1;
             const R Em = x * k, Ep = ((R)1 - x) * k;
             const R thm = (R)kMe / Em, thp = (R)kMe / Ep;
             R dm[3] = {t.u[0], t.u[1], t.u[2]};
@@ -402,9 +408,14 @@ __device__ inline void interact(const Ctx<P>& c, Track<P>& t, bool first, StepOu
         }
         o.proc = pos ? kBhabha : kMoller;
         R eps, phi;
-        const bool ok = pos ? sample_bhabha<R>(T, (R)ph.t_cut, key, eps, phi)
-                            : sample_moller<R>(T, (R)ph.t_cut, key, eps, phi);
-        if (!ok) o.rej_exhausted += 1;
+        const int am = pos ? kAlBhabha : kAlMoller;
+        if ((ph.fs_alias >> am) & 1) {
+            eps = alias_sample<R>(alias_view<R>(ph), am, T, (R)ph.t_cut, (R)ph.k_cut, key, phi);
+        } else {
+            const bool ok = pos ? sample_bhabha<R>(T, (R)ph.t_cut, key, eps, phi)
+                                : sample_moller<R>(T, (R)ph.t_cut, key, eps, phi);
+            if (!ok) o.rej_exhausted += 1;
+        }
         const R Td = eps * T;
         const R Tp = T - Td;
         const R m2 = (R)(2.0 * kMe);
@@ -430,7 +441,12 @@ __device__ inline void interact(const Ctx<P>& c, Track<P>& t, bool first, StepOu
         }
         o.proc = t.type == kPositron ? kBremsEp : kBremsEm;
         R k;
-        if (!sample_brems<R>(T, (R)ph.k_cut, key, k)) o.rej_exhausted += 1;
+        if ((ph.fs_alias >> kAlBrems) & 1) {
+            R phi_unused;
+            k = alias_sample<R>(alias_view<R>(ph), kAlBrems, T, (R)ph.t_cut, (R)ph.k_cut, key, phi_unused);
+        } else if (!sample_brems<R>(T, (R)ph.k_cut, key, k)) {
+            o.rej_exhausted += 1;
+        }
         child_ids(c, t, ids);
         add_child(o, kGamma, k, t.u, ids[0]);
         t.T = T - k;

@@ -130,9 +130,9 @@ def test_compaction_empty_outputs(gv):
     assert all(len(g) == 0 for g in got)
 
 
-def _single_step_case(gv, oracle_mod, geom, n, seed, precision):
-    orc = oracle_mod.Oracle(geom)
-    eng = _engine(gv, geom)
+def _single_step_case(gv, oracle_mod, geom, n, seed, precision, fs_alias=0):
+    orc = oracle_mod.Oracle(geom, run_spec={"fs_alias": fs_alias})
+    eng = _engine(gv, geom, fs_alias=fs_alias)
     st = gv_inputs.random_states(n, seed, geom)
     if precision == gv.PMIX:
         # the mixed path keeps direction and energy in float: compare on states
@@ -167,3 +167,43 @@ def test_single_step_mixed_parity(gv, oracle_mod, which):
     assert flips <= n * 2e-4, worst
     viol = {k: v for k, v in worst.items() if k.endswith("_violations")}
     assert sum(viol.values()) <= n * 1e-4, worst
+
+
+@pytest.mark.parametrize("precision", ["p64", "pmix"])
+def test_single_step_parity_table_sampling(gv, oracle_mod, precision):
+    """One step with every final state drawn from the alias tables."""
+    geom = gv_inputs.slab_calorimeter(50, (0.0, 4.0, 0.0))
+    n = 200_000
+    p = gv.P64 if precision == "p64" else gv.PMIX
+    flips, worst = _single_step_case(gv, oracle_mod, geom, n, 33, p, fs_alias=gv.FS_ALL)
+    print(f"\n[slab4T {precision} tables] flips {flips}/{n}; worst {worst}")
+    if p == gv.P64:
+        assert flips <= 2, worst
+        assert not any(k.endswith("_violations") for k in worst), worst
+    else:
+        assert flips <= n * 2e-4, worst
+        viol = {k: v for k, v in worst.items() if k.endswith("_violations")}
+        assert sum(viol.values()) <= n * 1e-4, worst
+
+
+def test_device_alias_tables_match_oracle(gv, oracle_mod):
+    """The device-built final-state tables equal the oracle's: densities to
+    1e-13, alias thresholds to 1e-12 and the alias columns exactly."""
+    import ctypes as C
+    geom = gv_inputs.slab_calorimeter(2)
+    orc = oracle_mod.Oracle(geom)
+    eng = _engine(gv, geom)
+    dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    bad_cols = 0
+    for m in range(5):
+        for j in range(121):
+            p, q, a = np.zeros(65), np.zeros(64), np.zeros(64, dtype=np.int32)
+            ok = orc.lib.or_alias_table(m, j, p.ctypes.data_as(dp), q.ctypes.data_as(dp), a.ctypes.data_as(ip))
+            v, gp, gq, ga = eng.alias_table(m, j)
+            assert v == bool(ok), (m, j)
+            if not ok:
+                continue
+            assert np.allclose(gp, p, rtol=1e-13, atol=0), (m, j)
+            assert np.allclose(gq, q, rtol=1e-12, atol=1e-14), (m, j)
+            bad_cols += int((ga != a).sum())
+    assert bad_cols == 0
