@@ -175,6 +175,8 @@ def run_gpu(args):
         log(f"[bench] table sampling: {tables['steps_per_s']:.3g} steps/s")
         eng.configure(fs_alias=0)
 
+    res["tables"] = tables
+
     # plain FP64 per-stage path on the same batch and first seed
     plain = None
     if args.plain_steps > 0:
@@ -213,8 +215,48 @@ def run_gpu(args):
         st = eng.stats()
         b64 = dict(steps_per_s=st["total_steps"] / dt, primaries_per_s=len(prim) / dt, ms_per_transport=dt * 1e3)
         log(f"[bench] batched FP64: {dt*1e3:.1f} ms")
-    res["tables"] = tables
+    # last: the single-slab leg sets up its own context (one per process)
+    res["testem5"] = run_testem5(args, gv, torch, eng.config) if args.testem5 else None
     return res, plain, b64
+
+
+def run_testem5(args, gv, torch, cfg):
+    """Single-slab transmission / reflection (10 MeV e- on 2 mm Pb, 20000
+    primaries): mixed-precision throughput and the fractions of primaries'
+    worth of e- leaving forward and backward, beside the oracle's."""
+    import numpy as np
+
+    import gv_inputs
+    geom, prim, seed = gv_inputs.workload("t5")
+    eng = gv.Engine(geom, driver=gv.DRIVER_BATCHED, precision=gv.PMIX, edep_on_device=1,
+                    hip_stream=cfg["hip_stream"])
+    edep = torch.zeros((len(prim), eng.n_cells), dtype=torch.float64, device="cuda:0")
+    eng.stage(prim)
+    eng.transport_staged(seed, edep.data_ptr())
+    ts, steps = [], 0
+    for k in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eng.transport_staged(seed, edep.data_ptr())
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+        steps += eng.stats()["total_steps"]
+    h = eng.escape_hist()
+    n = len(prim)
+    out = dict(workload="t5: 20000 x 10 MeV e- on 2 mm Pb", steps_per_s=steps / sum(ts),
+               ms_per_transport=float(np.median(ts)) * 1e3,
+               electrons_forward=float(h[1, :, 10:].sum() / n), electrons_backward=float(h[1, :, :10].sum() / n),
+               photons_forward=float(h[0, :, 10:].sum() / n), photons_backward=float(h[0, :, :10].sum() / n))
+    if not args.no_cpu:
+        import oracle
+        r = oracle.Oracle(geom).transport(prim, seed, n_threads=max(1, min(os.cpu_count() or 1, 16)))["escape_hist"]
+        out["oracle"] = dict(electrons_forward=float(r[1, :, 10:].sum() / n),
+                             electrons_backward=float(r[1, :, :10].sum() / n),
+                             photons_forward=float(r[0, :, 10:].sum() / n), photons_backward=float(r[0, :, :10].sum() / n))
+    eng.close()
+    log(f"[bench] testem5: {out['steps_per_s']:.3g} steps/s, e- forward {out['electrons_forward']:.4f} "
+        f"backward {out['electrons_backward']:.4f}")
+    return out
 
 
 def run_cpu_baseline(args):
@@ -262,6 +304,7 @@ def main():
     ap.add_argument("--occupancy", type=int, default=0)
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--testem5", type=int, default=1, help="run the single-slab leg")
     ap.add_argument("--table-steps", type=int, default=3,
                     help="timed transports with table (alias) final-state sampling")
     ap.add_argument("--fp64-batched", type=int, default=1)
@@ -328,6 +371,7 @@ def main():
         "speedup_vs_plain_fp64": (value / plain["steps_per_s"]) if plain else None,
         "batched_fp64": b64,
         "table_sampling": res["tables"],
+        "testem5": res["testem5"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),

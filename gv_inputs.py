@@ -229,6 +229,11 @@ def workload(name: str, n_events: int | None = None):
     if name == "c5":
         n = 2000 if n_events is None else n_events
         return barrel(), barrel_beam(n, 0xC5), 0xC5
+    if name == "t5":
+        # single-slab transmission / reflection (TestEm5-like, Sec. 4): 10 MeV
+        # e- at normal incidence on 2 mm of lead (0.36 X0), no field
+        n = 20000 if n_events is None else n_events
+        return single_slab("Pb", 0.2), beam(n, PDG_ELECTRON, 10.0), 0x75
     raise ValueError(f"unknown workload {name!r}")
 
 

@@ -247,6 +247,14 @@ int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out);
 /* Number of scoring cells of the current geometry. */
 int gv_n_cells(int32_t* out);
 
+/* Particles that left the world in the last transport, counted per type
+ * (gamma, e-, e+), kinetic-energy bin (5 per decade from 1 keV, 40 bins)
+ * and bin of the direction cosine with +z (20 bins on [-1, 1]): the
+ * transmission / reflection spectra of single-slab set-ups (Sec. 4).
+ * out: 3 x 40 x 20 uint64, row-major, caller-owned; n >= 2400.
+ * GV_E_NOT_INIT, GV_E_INVALID_ARG. */
+int gv_escape_hist(uint64_t* out, int64_t n);
+
 /* Test access to the final-state table of one model (GV_FS_*) at one node
  * (0..120, energy 0.1 MeV * 10^(node/20)): the density at 65 points (p), the
  * 64 alias thresholds (q) and alias columns, and whether the node lies above

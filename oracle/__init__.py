@@ -120,6 +120,7 @@ def load(rebuild: bool = False):
         for nm in (name, name + "_alias"):
             getattr(lib, nm).argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, dp]
             getattr(lib, nm).restype = C.c_int
+    lib.or_escape_hist.argtypes = [C.c_void_p]
     lib.or_alias_node_energy.argtypes = [C.c_int32]
     lib.or_alias_node_energy.restype = C.c_double
     lib.or_alias_table.argtypes = [C.c_int32, C.c_int32, dp, dp, ip]
@@ -218,7 +219,10 @@ class Oracle:
                                    _ptr(tn, C.c_int64))
         if rc != 0:
             raise RuntimeError("oracle transport failed: " + self.lib.or_error().decode())
-        out = dict(edep=edep, ledger=ledger, counters=dict(zip(COUNTER_NAMES, counters.tolist())))
+        hist = np.zeros((3, 40, 20), dtype=np.int64)
+        self.lib.or_escape_hist(hist.ctypes.data)
+        out = dict(edep=edep, ledger=ledger, counters=dict(zip(COUNTER_NAMES, counters.tolist())),
+                   escape_hist=hist)
         if trace is not None:
             out["trace"] = trace[: int(tn[0])]
         return out

@@ -459,6 +459,7 @@ typedef struct {
     double* edep;
     double* ledger;
     int64_t counters[OR_NCOUNT];
+    int64_t hist[OR_EH_SIZE];  /* escaping particles */
     or_trace* trace;
     int64_t trace_cap;
     int64_t* trace_n;
@@ -471,6 +472,26 @@ static int32_t type_of_pdg(int32_t pdg)
     if (pdg == 11) return OR_ELECTRON;
     if (pdg == -11) return OR_POSITRON;
     return -1;
+}
+
+static int64_t g_esc_hist[OR_EH_SIZE];
+
+int or_escape_hist(int64_t* out)
+{
+    if (!out) return -1;
+    memcpy(out, g_esc_hist, sizeof(g_esc_hist));
+    return 0;
+}
+
+/* one escaping particle into the histogram (H may be NULL) */
+static void escape_hist(int64_t* H, const trk_t* t)
+{
+    if (!H) return;
+    int eb = t->T > 0.0 ? (int)floor(log10(t->T / 1.0e-3) * 5.0) : 0;
+    eb = eb < 0 ? 0 : (eb > OR_EH_NE - 1 ? OR_EH_NE - 1 : eb);
+    int cb = (int)floor((t->dir[2] + 1.0) * 0.5 * OR_EH_NC);
+    cb = cb < 0 ? 0 : (cb > OR_EH_NC - 1 ? OR_EH_NC - 1 : cb);
+    H[(t->type * OR_EH_NE + eb) * OR_EH_NC + cb] += 1;
 }
 
 static void deposit(double* edep_row, double* L, int32_t vol, double e)
@@ -545,6 +566,7 @@ static void* worker(void* arg)
                 step_t si;
                 trk_t before = t;
                 one_step(J->seed, (uint32_t)ev, &t, &si, L, C);
+                if (si.status == ST_ESCAPED) escape_hist(J->hist, &t);
                 deposit(row, L, si.vol_pre, si.edep);
                 if (si.did_step) record(J, (uint32_t)ev, &before, &t, &si);
                 for (int c = 0; c < si.n_child; ++c) {
@@ -619,9 +641,11 @@ int or_transport(const or_primary* prim, int64_t n, uint64_t seed, int32_t n_thr
         J->trace_n = &tn;
         pthread_create(&th[t], NULL, worker, J);
     }
+    memset(g_esc_hist, 0, sizeof(g_esc_hist));
     for (int32_t t = 0; t < n_threads; ++t) {
         pthread_join(th[t], NULL);
         for (int c = 0; c < OR_NCOUNT; ++c) counters[c] += jobs[t].counters[c];
+        for (int b = 0; b < OR_EH_SIZE; ++b) g_esc_hist[b] += jobs[t].hist[b];
     }
     if (trace_n) *trace_n = tn < trace_cap ? tn : trace_cap;
     free(jobs);

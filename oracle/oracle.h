@@ -80,6 +80,14 @@ typedef struct {
     int32_t pad;
 } or_config;
 
+/* Histogram of escaping particles (single-slab observables, Sec. 4):
+ * [type][energy bin][bin of the direction cosine with +z], counts.  Energy
+ * bins: 5 per decade from 1 keV (40 bins); cosine bins: 20 on [-1, 1]. */
+#define OR_EH_NE 40
+#define OR_EH_NC 20
+#define OR_EH_SIZE (3 * OR_EH_NE * OR_EH_NC)
+int or_escape_hist(int64_t* out);   /* the histogram of the last or_transport */
+
 /* Final-state models with a table (alias) sampler; bit m of fs_alias */
 enum { OR_AL_COMPTON = 0, OR_AL_PAIR = 1, OR_AL_BREMS = 2, OR_AL_MOLLER = 3, OR_AL_BHABHA = 4,
        OR_AL_NMOD = 5 };

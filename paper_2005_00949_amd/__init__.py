@@ -123,6 +123,7 @@ def load():
     lib.gv_finalize.restype = None
     lib.gv_debug_step.argtypes = [C.c_int32, C.c_int64, C.POINTER(DebugIO)]
     lib.gv_alias_table.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gv_escape_hist.argtypes = [C.c_void_p, C.c_int64]
     _lib = lib
     return lib
 
@@ -321,6 +322,12 @@ class Engine:
         io.d_bnd, io.vol, io.vol_pre, io.safety = _p(out["d_bnd"]), _p(out["next"]), _p(out["vol"]), _p(out["safety"])
         self._debug(DBG_GEOM, n, io)
         return out
+
+    def escape_hist(self):
+        """Escaping particles of the last transport: counts [type, energy bin, cos bin]."""
+        h = np.zeros((3, 40, 20), dtype=np.uint64)
+        _check(self.lib.gv_escape_hist(h.ctypes.data, h.size))
+        return h.astype(np.int64)
 
     def alias_table(self, model, node):
         """Final-state table of one model at one node: (valid, p, q, alias)."""

@@ -94,7 +94,24 @@ struct Sinks {
     unsigned long long* trace_n;
     long long trace_cap;
     int fixed;                    // deposits and ledger held as unsigned 2^-40 MeV integers
+    unsigned long long* esc_hist; // escaping particles [type][energy bin][cos bin]
 };
+
+// Escaping particles, binned like the single-slab observables of Sec. 4:
+// 5 energy bins per decade from 1 keV (40) x 20 bins of the direction cosine
+// with +z, per particle type; integer counts, so any arrival order gives the
+// same histogram.
+constexpr int kEhNE = 40, kEhNC = 20, kEhSize = 3 * kEhNE * kEhNC;
+template <class R>
+__device__ __forceinline__ void escape_count(const Sinks& S, int type, R T, R uz)
+{
+    const double Td = (double)T;
+    int eb = Td > 0.0 ? (int)floor(log10(Td / 1.0e-3) * 5.0) : 0;
+    eb = eb < 0 ? 0 : (eb > kEhNE - 1 ? kEhNE - 1 : eb);
+    int cb = (int)floor(((double)uz + 1.0) * 0.5 * kEhNC);
+    cb = cb < 0 ? 0 : (cb > kEhNC - 1 ? kEhNC - 1 : cb);
+    atomicAdd(&S.esc_hist[(type * kEhNE + eb) * kEhNC + cb], 1ull);
+}
 
 // Fixed-point scoring: every deposit is rounded once to an integer number of
 // 2^-40 MeV and summed with integer atomics, so the sums do not depend on the
@@ -723,6 +740,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             acc_add(A.S, acc, o.edep);
             if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
             account_rare(A.S, t.ev, o, cnt_lds);
+            if (o.status == kEscaped) escape_count(A.S, TY, t.T, t.u[2]);
             if (o.status != kAlive || o.nchild > 0) break;
         }
         dep_add(dc, A.S, t.ev, acc_vol, acc);
@@ -967,6 +985,7 @@ __global__ void k_plain_finish(PlainArgs A)
         }
         deposit(A.S, t.ev, A.vol_pre[i], o.edep);
         account_rare(A.S, t.ev, o, cnt_lds);
+        if (o.status == kEscaped) escape_count(A.S, t.type, t.T, t.u[2]);
         A.o[i] = o;
     }
     __syncthreads();

@@ -172,6 +172,7 @@ struct Lib {
     DBuf<unsigned long long> counters;
     DBuf<double> edep, ledger;
     DBuf<gv_trace_rec> trace;
+    DBuf<unsigned long long> esc_hist;
     DBuf<unsigned long long> trace_n;
     DBuf<PrimDev> prim;
     DBuf<uint32_t> prim_slot;
@@ -278,6 +279,7 @@ void release_all()
     L.edep.release();
     L.ledger.release();
     L.trace.release();
+    L.esc_hist.release();
     L.trace_n.release();
     L.prim.release();
     L.prim_slot.release();
@@ -512,6 +514,10 @@ int ensure_common(int64_t n_events)
         HIPCHK(L.trace.ensure((size_t)L.cfg.trace_cap));
     }
     HIPCHK(L.trace_n.ensure(1));
+    if (!L.esc_hist.p) {
+        drop_graph();
+        HIPCHK(L.esc_hist.ensure(kEhSize));
+    }
     if (!L.h_ctrl) HIPCHK(hipHostMalloc((void**)&L.h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     if (!L.ev0) HIPCHK(hipEventCreate(&L.ev0));
     if (!L.ev1) HIPCHK(hipEventCreate(&L.ev1));
@@ -549,6 +555,7 @@ Sinks make_sinks()
     S.trace_n = L.trace_n.p;
     S.trace_cap = L.cfg.trace_cap;
     S.fixed = L.cfg.deposit_mode == GV_DEPOSIT_FIXED ? 1 : 0;
+    S.esc_hist = L.esc_hist.p;
     return S;
 }
 
@@ -841,6 +848,7 @@ int reset_run_buffers(int64_t n_events)
     HIPCHK(hipMemsetAsync(L.ledger.p, 0, (size_t)n_events * 4 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(L.counters.p, 0, kNCount * sizeof(unsigned long long), s));
     HIPCHK(hipMemsetAsync(L.trace_n.p, 0, sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(L.esc_hist.p, 0, kEhSize * sizeof(unsigned long long), s));
     return GV_OK;
 }
 
@@ -1323,6 +1331,19 @@ int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out)
     const int64_t n = std::min<int64_t>(cap, L.stats.trace_records);
     if (n > 0) HIPCHK(hipMemcpy(out, L.trace.p, (size_t)n * sizeof(gv_trace_rec), hipMemcpyDeviceToHost));
     *n_out = n;
+    return GV_OK;
+}
+
+int gv_escape_hist(uint64_t* out, int64_t n)
+{
+    if (!L.ready) return fail(GV_E_NOT_INIT, "gv_init has not succeeded");
+    if (!out || n < kEhSize) return fail(GV_E_INVALID_ARG, "null output or fewer than 2400 entries");
+    if (!L.esc_hist.p) {
+        std::memset(out, 0, kEhSize * sizeof(uint64_t));
+        return GV_OK;
+    }
+    HIPCHK(hipMemcpyAsync(out, L.esc_hist.p, kEhSize * sizeof(uint64_t), hipMemcpyDeviceToHost, stream()));
+    HIPCHK(hipStreamSynchronize(stream()));
     return GV_OK;
 }
 

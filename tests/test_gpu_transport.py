@@ -13,6 +13,8 @@
   paired test, |mean difference| <= 3 sigma_paired and <= 0.5% for layers
   holding at least 1% of the deposit.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -270,3 +272,29 @@ def test_fixed_point_scores_bit_identical(gv, prec):
         assert np.array_equal(led, runs[0][1])
     ef = gv.Engine(geom, precision=p).transport(prim, seed)
     assert np.allclose(runs[0][0], ef, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("mode", ["plain64", "batch64", "batchmix"])
+def test_escape_histogram_vs_oracle(gv, oracle_mod, mode):
+    """Single-slab transmission / reflection spectra (10 MeV e- on 2 mm Pb):
+    the FP64 drivers count exactly the oracle's escapes, bin for bin; the
+    mixed path agrees in the transmitted and reflected fractions of each
+    particle type within 3 sigma."""
+    geom, prim, seed = gv_inputs.workload("t5", 3000)
+    ref = oracle_mod.Oracle(geom).transport(prim, seed)
+    cfg = {"plain64": dict(driver=gv.DRIVER_PLAIN, precision=gv.P64),
+           "batch64": dict(precision=gv.P64), "batchmix": dict(precision=gv.PMIX)}[mode]
+    eng = gv.Engine(geom, **cfg)
+    eng.transport(prim, seed)
+    h, r = eng.escape_hist(), ref["escape_hist"]
+    assert h.sum() == eng.stats()["escaped"]
+    if mode != "batchmix":
+        assert np.array_equal(h, r)
+        return
+    n = len(prim)
+    for ty in range(3):
+        for half in (slice(0, 10), slice(10, 20)):
+            a, b = h[ty, :, half].sum() / n, r[ty, :, half].sum() / n
+            sig = math.sqrt(max(b * (1 - b), 1.0 / n) / n)
+            print(f"\n[t5 type {ty} {'fwd' if half.start else 'back'}] gpu {a:.4f} oracle {b:.4f}")
+            assert abs(a - b) <= 3 * math.sqrt(2) * sig + 1e-12

@@ -104,3 +104,22 @@ def test_testem3_shower_sanity(oracle_mod, capsys):
     tot_paper = paper["Pb"] + paper["lAr"]
     assert 0.8 * tot_paper < pb + lar < 1.02 * 10000
     assert 0.6 < (lar / (pb + lar)) / (paper["lAr"] / tot_paper) < 1.4
+
+
+def test_escape_histogram_counts_and_transparent_slab(oracle_mod):
+    """The escape histogram counts every escaping particle once; through a
+    slab too thin to interact, every electron leaves forward at its energy:
+    all counts in the bin of 10 MeV and of cos = 1."""
+    geom, prim, seed = gv_inputs.workload("t5", 300)
+    r = oracle_mod.Oracle(geom).transport(prim, seed)
+    assert r["escape_hist"].sum() == r["counters"]["escaped"]
+    thin = gv_inputs.single_slab("lAr", 1e-9)
+    p12 = gv_inputs.beam(300, gv_inputs.PDG_ELECTRON, 12.0)     # 12 MeV: inside a bin
+    r = oracle_mod.Oracle(thin).transport(p12, seed)
+    h = r["escape_hist"]
+    eb = int(math.floor(math.log10(12.0 / 1e-3) * 5))
+    assert h.sum() == len(p12) and h[1, eb, 19] == len(p12)
+    # 2 mm of lead: most primaries get through, a few percent come back
+    r = oracle_mod.Oracle(geom).transport(prim, seed)
+    fwd, back = r["escape_hist"][1, :, 10:].sum(), r["escape_hist"][1, :, :10].sum()
+    assert fwd > 0.5 * len(prim) and 0 < back < 0.3 * len(prim)
