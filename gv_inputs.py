@@ -19,6 +19,9 @@ the barrel is a synthetic stand-in for the CMS setup of Sec. 6):
 * ``c5``: cylindrical barrel (10 Si shells, PbWO4 shell, 20 brass/polystyrene
   pairs) in a 3.8 T solenoidal field along z; 2000 events of 50 GeV e-/gamma
   (event mod 2) with eta uniform in [-1, 1], phi uniform.
+* ``c5m``: ``c5`` in the field of a finite solenoid (coil radius 315 cm,
+  half-length 630 cm, 3.8 T at the centre) instead of a uniform one.
+* ``t5``: 10 MeV e- at normal incidence on 2 mm of lead, no field.
 
 Units: cm, MeV, g/cm^3, tesla.
 """
@@ -75,7 +78,8 @@ TABLE_SPEC = dict(e_min=1.0e-3, bins_per_decade=100, n_nodes=801,
 
 # Transport constants that are run parameters rather than physics.
 RUN_SPEC = dict(chord_tol=1.0e-3, push=1.0e-7, rk_frac=0.05,
-                max_steps=1 << 20, field_method=0, fs_alias=0)
+                max_steps=1 << 20, field_method=0, fs_alias=0,
+                rk_tol=1.0e-6, rk_max_sub=10000)
 
 
 def material_list(names):
@@ -121,7 +125,14 @@ def single_slab(material: str, thickness_cm: float, half_xy: float = 1.0e4):
                 n_cells=1)
 
 
-def barrel(b_tesla=(0.0, 0.0, 3.8)):
+MAP_UNIFORM = 0
+MAP_SOLENOID = 1
+# synthetic solenoid map (stand-in for an interpolated detector field map):
+# coil radius and half-length in cm, central field from B[2]
+SOLENOID = (315.0, 630.0)
+
+
+def barrel(b_tesla=(0.0, 0.0, 3.8), field_map=MAP_UNIFORM, sol=SOLENOID):
     """Cylindrical barrel; every shell has half-length 350 cm.
 
     Shells from r = 0: beam vacuum [0, 3); ten 300 um Si shells at
@@ -163,6 +174,8 @@ def barrel(b_tesla=(0.0, 0.0, 3.8)):
                 env=np.array([350.0, 0.0], dtype=np.float64),
                 world=np.array([300.0, 400.0, 0.0, 0.0], dtype=np.float64),
                 B=np.array(b_tesla, dtype=np.float64),
+                field_map=field_map,
+                sol=np.array(sol if field_map == MAP_SOLENOID else (0.0, 0.0), dtype=np.float64),
                 n_cells=cell)
 
 
@@ -229,6 +242,10 @@ def workload(name: str, n_events: int | None = None):
     if name == "c5":
         n = 2000 if n_events is None else n_events
         return barrel(), barrel_beam(n, 0xC5), 0xC5
+    if name == "c5m":
+        # the barrel in the solenoid map (field integrated by adaptive RK45)
+        n = 2000 if n_events is None else n_events
+        return barrel(field_map=MAP_SOLENOID), barrel_beam(n, 0xC5), 0xC5
     if name == "t5":
         # single-slab transmission / reflection (TestEm5-like, Sec. 4): 10 MeV
         # e- at normal incidence on 2 mm of lead (0.36 X0), no field

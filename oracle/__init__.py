@@ -22,7 +22,8 @@ NPROC = len(PROC_NAMES)
 COUNTER_NAMES = (["steps_gamma", "steps_electron", "steps_positron",
                   "tracks_gamma", "tracks_electron", "tracks_positron"]
                  + ["proc_" + p for p in PROC_NAMES]
-                 + ["escaped", "killed", "rejection_exhausted", "trace_dropped"])
+                 + ["escaped", "killed", "rejection_exhausted", "trace_dropped",
+                    "rk_substeps", "rk_rejected"])
 LEDGER_NAMES = ["escaped", "killed", "n_pair", "n_annih"]
 TABLE_NAMES = ["compton", "pair", "moller", "brems_em", "S_em", "R_em",
                "bhabha", "brems_ep", "S_ep", "R_ep"]
@@ -38,14 +39,23 @@ class Material(C.Structure):
 class Geometry(C.Structure):
     _fields_ = [("axis", C.c_int32), ("n_vol", C.c_int32), ("bounds", C.POINTER(C.c_double)),
                 ("material", C.POINTER(C.c_int32)), ("cell", C.POINTER(C.c_int32)),
-                ("env", C.c_double * 2), ("world", C.c_double * 4), ("B", C.c_double * 3)]
+                ("env", C.c_double * 2), ("world", C.c_double * 4), ("B", C.c_double * 3),
+                ("field_map", C.c_int32), ("pad", C.c_int32), ("sol", C.c_double * 2)]
+
+
+class Field(C.Structure):
+    _fields_ = [("map", C.c_int32), ("pad", C.c_int32), ("B", C.c_double * 3), ("sol", C.c_double * 2)]
 
 
 class Config(C.Structure):
     _fields_ = [("e_min", C.c_double), ("bins_per_decade", C.c_double), ("n_nodes", C.c_int32),
                 ("field_method", C.c_int32), ("t_cut", C.c_double), ("k_cut", C.c_double),
                 ("t_track", C.c_double), ("chord_tol", C.c_double), ("push", C.c_double),
-                ("rk_frac", C.c_double), ("max_steps", C.c_int64), ("fs_alias", C.c_int32), ("pad", C.c_int32)]
+                ("rk_frac", C.c_double), ("max_steps", C.c_int64), ("fs_alias", C.c_int32), ("pad", C.c_int32),
+                ("rk_tol", C.c_double), ("rk_max_sub", C.c_int32), ("pad2", C.c_int32)]
+
+MAP_UNIFORM, MAP_SOLENOID = 0, 1
+FIELD_HELIX, FIELD_RK4, FIELD_RK45 = 0, 1, 2
 
 
 TRACE_DTYPE = np.dtype([("tid", "<u8"), ("event", "<u4"), ("nstep", "<u4"), ("type", "<i4"),
@@ -112,6 +122,13 @@ def load(rebuild: bool = False):
     lib.or_safety.restype = C.c_double
     lib.or_helix_move.argtypes = [C.c_int32, C.c_double, dp, C.c_double, dp, dp]
     lib.or_rk4_move.argtypes = [C.c_int32, C.c_double, dp, C.c_double, C.c_int32, dp, dp]
+    fp = C.POINTER(Field)
+    lib.or_field_eval.argtypes = [fp, dp, dp]
+    lib.or_rk4_field_move.argtypes = [C.c_int32, C.c_double, fp, C.c_double, C.c_int32, dp, dp]
+    lib.or_rk45_move.argtypes = [C.c_int32, C.c_double, fp, C.c_double, C.c_double, C.c_int32,
+                                 dp, dp, dp, ip]
+    lib.or_rk45_move.restype = C.c_int32
+    lib.or_dp45_tableau.argtypes = [dp, dp, dp, dp]
     lib.or_highland.argtypes = [C.c_int32, C.c_double, C.c_double]
     lib.or_highland.restype = C.c_double
     lib.or_rotate.argtypes = [dp, C.c_double, C.c_double, C.c_double]
@@ -182,6 +199,9 @@ class Oracle:
             g.world[i] = float(geom["world"][i])
         for i in range(3):
             g.B[i] = float(geom["B"][i])
+        g.field_map = int(geom.get("field_map", MAP_UNIFORM))
+        sol = geom.get("sol", (0.0, 0.0))
+        g.sol[0], g.sol[1] = float(sol[0]), float(sol[1])
         cfg = Config()
         cfg.e_min = ts["e_min"]
         cfg.bins_per_decade = ts["bins_per_decade"]
@@ -195,6 +215,8 @@ class Oracle:
         cfg.max_steps = rs["max_steps"]
         cfg.field_method = rs["field_method"]
         cfg.fs_alias = rs.get("fs_alias", 0)
+        cfg.rk_tol = rs["rk_tol"]
+        cfg.rk_max_sub = rs["rk_max_sub"]
         rc = self.lib.or_setup(arr, len(mats), C.byref(g), C.byref(cfg))
         if rc != 0:
             raise RuntimeError("oracle setup failed: " + self.lib.or_error().decode())
@@ -300,3 +322,59 @@ def stream(seed, event, tid, nstep, purpose):
     o = (C.c_uint32 * 4)()
     lib.or_stream(seed, event, tid, nstep, purpose, o)
     return list(o)
+
+
+def make_field(map_kind=MAP_UNIFORM, B=(0.0, 0.0, 0.0), sol=(0.0, 0.0)) -> Field:
+    f = Field()
+    f.map = map_kind
+    for i in range(3):
+        f.B[i] = float(B[i])
+    f.sol[0], f.sol[1] = float(sol[0]), float(sol[1])
+    return f
+
+
+def field_eval(field: Field, x):
+    lib = load()
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(3)
+    lib.or_field_eval(C.byref(field), _ptr(xa, C.c_double), _ptr(out, C.c_double))
+    return out
+
+
+def rk45_move(type_, ekin, field: Field, s, tol, max_sub, pos, direction):
+    """Adaptive Dormand-Prince move; returns (pos, dir, s_done, n_accepted, n_rejected)."""
+    lib = load()
+    p = np.array(pos, dtype=np.float64)
+    d = np.array(direction, dtype=np.float64)
+    sd = C.c_double()
+    nr = C.c_int32()
+    na = lib.or_rk45_move(type_, ekin, C.byref(field), s, tol, max_sub, _ptr(p, C.c_double),
+                          _ptr(d, C.c_double), C.byref(sd), C.byref(nr))
+    return p, d, sd.value, int(na), int(nr.value)
+
+
+def rk4_field_move(type_, ekin, field: Field, s, nsub, pos, direction):
+    lib = load()
+    p = np.array(pos, dtype=np.float64)
+    d = np.array(direction, dtype=np.float64)
+    lib.or_rk4_field_move(type_, ekin, C.byref(field), s, nsub, _ptr(p, C.c_double), _ptr(d, C.c_double))
+    return p, d
+
+
+def helix_move(type_, ekin, B, s, pos, direction):
+    lib = load()
+    Ba = np.ascontiguousarray(B, dtype=np.float64)
+    p = np.array(pos, dtype=np.float64)
+    d = np.array(direction, dtype=np.float64)
+    lib.or_helix_move(type_, ekin, _ptr(Ba, C.c_double), s, _ptr(p, C.c_double), _ptr(d, C.c_double))
+    return p, d
+
+
+def dp45_tableau():
+    lib = load()
+    a = np.zeros(49)
+    b = np.zeros(7)
+    bh = np.zeros(7)
+    c = np.zeros(7)
+    lib.or_dp45_tableau(_ptr(a, C.c_double), _ptr(b, C.c_double), _ptr(bh, C.c_double), _ptr(c, C.c_double))
+    return a.reshape(7, 7), b, bh, c

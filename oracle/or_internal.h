@@ -25,6 +25,7 @@ typedef struct {
     int32_t* vmat;
     int32_t* vcell;
     double env[2], world[4], B[3];
+    or_field field;
     or_config cfg;
     double* node_E;
     double* tab[OR_MAX_MATS][OR_NTAB];

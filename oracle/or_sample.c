@@ -1,7 +1,8 @@
 /*
  * Oracle kinematics (test infrastructure only): charged-particle motion in a
- * uniform magnetic field (Sec. 3.6: exact helix, or classic 4th-order
- * Runge-Kutta on du/ds = (q kB / p) u x B, dx/ds = u), direction rotation,
+ * magnetic field (Sec. 3.6: exact helix in the field at the start point,
+ * classic 4th-order Runge-Kutta, or adaptive Dormand-Prince 5(4), on
+ * du/ds = (q kB / p) u x B(x), dx/ds = u), direction rotation,
  * Highland multiple scattering, and the final-state samplers of Sec. 3.5 by
  * composition-rejection.
  *
@@ -60,23 +61,71 @@ static void lorentz(double kq, const double B[3], const double u[3], double out[
     out[2] = kq * (u[0] * B[1] - u[1] * B[0]);
 }
 
-void or_rk4_move(int32_t type, double ekin, const double B[3], double s, int32_t nsub,
-                 double pos[3], double dir[3])
+/* Field of a finite solenoid along z (coil radius R, half-length L, central
+ * field B0).  On the axis a uniform current sheet gives
+ *   g(z) = B0 f(z) / f(0),  f(z) = (z+L)/sqrt(R^2+(z+L)^2) - (z-L)/sqrt(R^2+(z-L)^2);
+ * off the axis the axisymmetric field is expanded to second order in r:
+ *   B_r = -(r/2) g'(z),  B_z = g(z) - (r^2/4) g''(z),
+ * which has zero curl exactly and a divergence of order r^2 g'''. */
+static void solenoid_field(double B0, double R, double L, const double x[3], double out[3])
+{
+    double R2 = R * R;
+    double f0 = 2.0 * L / sqrt(R2 + L * L);
+    double c = B0 / f0;
+    double a = x[2] + L, b = x[2] - L;
+    double qa = R2 + a * a, qb = R2 + b * b;
+    double sa = sqrt(qa), sb = sqrt(qb);
+    double g = c * (a / sa - b / sb);
+    double g1 = c * R2 * (1.0 / (qa * sa) - 1.0 / (qb * sb));               /* g'  */
+    double g2 = -3.0 * c * R2 * (a / (qa * qa * sa) - b / (qb * qb * sb));  /* g'' */
+    double r2 = x[0] * x[0] + x[1] * x[1];
+    out[0] = -0.5 * x[0] * g1;
+    out[1] = -0.5 * x[1] * g1;
+    out[2] = g - 0.25 * r2 * g2;
+}
+
+void or_field_eval(const or_field* f, const double x[3], double B[3])
+{
+    if (f->map == OR_MAP_SOLENOID) {
+        solenoid_field(f->B[2], f->sol[0], f->sol[1], x, B);
+    } else {
+        B[0] = f->B[0];
+        B[1] = f->B[1];
+        B[2] = f->B[2];
+    }
+}
+
+void or_rk4_field_move(int32_t type, double ekin, const or_field* f, double s, int32_t nsub,
+                       double pos[3], double dir[3])
 {
     double p = sqrt(ekin * (ekin + 2.0 * OR_ME));
     double kq = charge_of(type) * OR_KB / p;
     double h = s / nsub;
     for (int i = 0; i < nsub; ++i) {
-        double k1u[3], k2u[3], k3u[3], k4u[3], u2[3], u3[3], u4[3];
-        lorentz(kq, B, dir, k1u);
-        for (int a = 0; a < 3; ++a) u2[a] = dir[a] + 0.5 * h * k1u[a];
-        lorentz(kq, B, u2, k2u);
-        for (int a = 0; a < 3; ++a) u3[a] = dir[a] + 0.5 * h * k2u[a];
-        lorentz(kq, B, u3, k3u);
-        for (int a = 0; a < 3; ++a) u4[a] = dir[a] + h * k3u[a];
-        lorentz(kq, B, u4, k4u);
+        double k1u[3], k2u[3], k3u[3], k4u[3], u2[3], u3[3], u4[3], x2[3], x3[3], x4[3];
+        double B1[3], B2[3], B3[3], B4[3];
+        /* dx/ds = u: the position stages are the u stages */
+        or_field_eval(f, pos, B1);
+        lorentz(kq, B1, dir, k1u);
         for (int a = 0; a < 3; ++a) {
-            /* dx/ds = u: the position stages are the u stages */
+            u2[a] = dir[a] + 0.5 * h * k1u[a];
+            x2[a] = pos[a] + 0.5 * h * dir[a];
+        }
+        or_field_eval(f, x2, B2);
+        lorentz(kq, B2, u2, k2u);
+        for (int a = 0; a < 3; ++a) {
+            u3[a] = dir[a] + 0.5 * h * k2u[a];
+            x3[a] = pos[a] + 0.5 * h * u2[a];
+        }
+        or_field_eval(f, x3, B3);
+        lorentz(kq, B3, u3, k3u);
+        for (int a = 0; a < 3; ++a) {
+            u4[a] = dir[a] + h * k3u[a];
+            x4[a] = pos[a] + h * u3[a];
+        }
+        or_field_eval(f, x4, B4);
+        lorentz(kq, B4, u4, k4u);
+        for (int a = 0; a < 3; ++a) {
             pos[a] += h / 6.0 * (dir[a] + 2.0 * u2[a] + 2.0 * u3[a] + u4[a]);
             dir[a] += h / 6.0 * (k1u[a] + 2.0 * k2u[a] + 2.0 * k3u[a] + k4u[a]);
         }
@@ -85,6 +134,118 @@ void or_rk4_move(int32_t type, double ekin, const double B[3], double s, int32_t
     dir[0] /= nn;
     dir[1] /= nn;
     dir[2] /= nn;
+}
+
+void or_rk4_move(int32_t type, double ekin, const double B[3], double s, int32_t nsub,
+                 double pos[3], double dir[3])
+{
+    or_field f = {OR_MAP_UNIFORM, 0, {B[0], B[1], B[2]}, {0.0, 0.0}};
+    or_rk4_field_move(type, ekin, &f, s, nsub, pos, dir);
+}
+
+/* Dormand & Prince (1980), RK5(4)7M: rows of the stage matrix, the 5th-order
+ * weights (equal to the last row, so the last stage is the derivative at the
+ * new point) and the embedded 4th-order weights. */
+static const double DP_A[7][6] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0, 0.0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0.0, 0.0, 0.0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0.0, 0.0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0.0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
+                               -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+static const double DP_BH[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
+                                -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+
+void or_dp45_tableau(double* a, double* b, double* bh, double* c)
+{
+    for (int i = 0; i < 7; ++i) {
+        for (int j = 0; j < 7; ++j) a[7 * i + j] = j < 6 ? DP_A[i][j] : 0.0;
+        b[i] = DP_B[i];
+        bh[i] = DP_BH[i];
+        c[i] = DP_C[i];
+    }
+}
+
+/* One stage derivative of y = (x, u): dx/ds = u, du/ds = kq u x B(x). */
+static void dp_deriv(const or_field* f, double kq, const double y[6], double k[6])
+{
+    double B[3];
+    or_field_eval(f, y, B);
+    k[0] = y[3];
+    k[1] = y[4];
+    k[2] = y[5];
+    lorentz(kq, B, y + 3, k + 3);
+}
+
+/* Adaptive Dormand-Prince integration of the equation of motion over the
+ * path length s (Sec. 3.6: a Runge-Kutta step with an error estimate, then
+ * the accept / retry / next-size decision).
+ *   error measure of a substep of length h, with e = b - bh:
+ *     err = max( max_a |sum_j e_j kx_j[a]|,  max_a |h sum_j e_j ku_j[a]| )
+ *   (position error per unit length, and direction error); accepted when
+ *   err <= tol.  The first attempt covers the whole remaining length; a
+ *   rejected attempt halves h, an accepted one with err <= tol/32 doubles
+ *   the next h; h never passes the end of the interval.  Stops after
+ *   max_sub attempts.  Sums over stages run in stage order. */
+int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, double tol,
+                     int32_t max_sub, double pos[3], double dir[3], double* s_done, int32_t* n_rej)
+{
+    double p = sqrt(ekin * (ekin + 2.0 * OR_ME));
+    double kq = charge_of(type) * OR_KB / p;
+    double y[6] = {pos[0], pos[1], pos[2], dir[0], dir[1], dir[2]};
+    double done = 0.0, h = s;
+    int32_t acc = 0, rej = 0;
+    *s_done = 0.0;
+    *n_rej = 0;
+    if (!(s > 0.0)) return 0;
+    while (acc + rej < max_sub) {
+        double rem = s - done;
+        int last = h >= rem;
+        if (last) h = rem;
+        double k[7][6], yi[6];
+        dp_deriv(f, kq, y, k[0]);
+        for (int i = 1; i < 7; ++i) {
+            for (int c = 0; c < 6; ++c) {
+                double sum = DP_A[i][0] * k[0][c];
+                for (int j = 1; j < i; ++j) sum += DP_A[i][j] * k[j][c];
+                yi[c] = y[c] + h * sum;
+            }
+            dp_deriv(f, kq, yi, k[i]);
+        }
+        /* yi now holds the 5th-order solution (the last row equals DP_B) */
+        double err = 0.0;
+        for (int c = 0; c < 6; ++c) {
+            double e = (DP_B[0] - DP_BH[0]) * k[0][c];
+            for (int j = 1; j < 7; ++j) e += (DP_B[j] - DP_BH[j]) * k[j][c];
+            if (c >= 3) e = h * e;
+            if (fabs(e) > err) err = fabs(e);
+        }
+        if (err <= tol) {
+            ++acc;
+            for (int c = 0; c < 6; ++c) y[c] = yi[c];
+            if (last) {
+                done = s;
+                break;
+            }
+            done += h;
+            if (err <= tol * (1.0 / 32.0)) h *= 2.0;
+        } else {
+            ++rej;
+            h *= 0.5;
+        }
+    }
+    double nn = sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+    for (int a = 0; a < 3; ++a) {
+        pos[a] = y[a];
+        dir[a] = y[3 + a] / nn;
+    }
+    *s_done = done;
+    *n_rej = rej;
+    return acc;
 }
 
 /* ---------------- rotation and MSC ---------------- */

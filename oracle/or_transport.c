@@ -84,6 +84,25 @@ int or_setup(const or_material* mats, int32_t n_mats, const or_geometry* geom, c
     memcpy(G.env, geom->env, sizeof(G.env));
     memcpy(G.world, geom->world, sizeof(G.world));
     memcpy(G.B, geom->B, sizeof(G.B));
+    if (geom->field_map != OR_MAP_UNIFORM && geom->field_map != OR_MAP_SOLENOID) {
+        or_set_error("unknown field map");
+        return -1;
+    }
+    if (geom->field_map == OR_MAP_SOLENOID &&
+        (G.B[0] != 0.0 || G.B[1] != 0.0 || !(geom->sol[0] > 0.0) || !(geom->sol[1] > 0.0))) {
+        or_set_error("solenoid needs B along z and a positive radius and half-length");
+        return -1;
+    }
+    if (G.cfg.field_method < OR_FIELD_HELIX || G.cfg.field_method > OR_FIELD_RK45 ||
+        (G.cfg.field_method == OR_FIELD_RK45 && (!(G.cfg.rk_tol > 0.0) || G.cfg.rk_max_sub < 1))) {
+        or_set_error("bad field method or RK45 settings");
+        return -1;
+    }
+    G.field.map = geom->field_map;
+    G.field.pad = 0;
+    memcpy(G.field.B, geom->B, sizeof(G.field.B));
+    G.field.sol[0] = geom->sol[0];
+    G.field.sol[1] = geom->sol[1];
     G.n_cells = 0;
     for (int32_t v = 0; v < G.n_vol; ++v) {
         if (!(G.bounds[v + 1] > G.bounds[v])) {
@@ -339,7 +358,9 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
 
     /* ---- Propagation ---- */
     const double T_pre = t->T;
-    const double Bm = sqrt(G.B[0] * G.B[0] + G.B[1] * G.B[1] + G.B[2] * G.B[2]);
+    double Bl[3]; /* the field at the pre-step point */
+    or_field_eval(&G.field, t->pos, Bl);
+    const double Bm = sqrt(Bl[0] * Bl[0] + Bl[1] * Bl[1] + Bl[2] * Bl[2]);
     double s;
     int lim, crossed = 0;
     if (!charged || Bm == 0.0) {
@@ -359,7 +380,7 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
     } else {
         double p = sqrt(T_pre * (T_pre + 2.0 * OR_ME));
         /* transverse momentum relative to B: p |u x B/|B|| */
-        double b[3] = {G.B[0] / Bm, G.B[1] / Bm, G.B[2] / Bm};
+        double b[3] = {Bl[0] / Bm, Bl[1] / Bm, Bl[2] / Bm};
         double cx = t->dir[1] * b[2] - t->dir[2] * b[1];
         double cy = t->dir[2] * b[0] - t->dir[0] * b[2];
         double cz = t->dir[0] * b[1] - t->dir[1] * b[0];
@@ -383,9 +404,20 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
             double nsub = (rcurv < INF_LEN) ? ceil(s / (cf->rk_frac * rcurv)) : 1.0;
             if (nsub < 1.0) nsub = 1.0;
             if (nsub > 100000.0) nsub = 100000.0;
-            or_rk4_move(t->type, T_pre, G.B, s, (int32_t)nsub, t->pos, t->dir);
+            or_rk4_field_move(t->type, T_pre, &G.field, s, (int32_t)nsub, t->pos, t->dir);
+        } else if (cf->field_method == OR_FIELD_RK45) {
+            double s_done;
+            int32_t n_rej;
+            int32_t n_acc = or_rk45_move(t->type, T_pre, &G.field, s, cf->rk_tol, cf->rk_max_sub,
+                                         t->pos, t->dir, &s_done, &n_rej);
+            C[OR_C_RK_SUB] += n_acc;
+            C[OR_C_RK_REJ] += n_rej;
+            if (s_done < s) { /* attempts ran out: the step ends where integration stopped */
+                s = s_done;
+                lim = OR_LIM_FIELD;
+            }
         } else {
-            or_helix_move(t->type, T_pre, G.B, s, t->pos, t->dir);
+            or_helix_move(t->type, T_pre, Bl, s, t->pos, t->dir);
         }
         int32_t nv = or_locate(t->pos);
         if (nv != t->vol) {

@@ -38,7 +38,9 @@ enum { OR_PURP_STEP = 0, OR_PURP_MSC = 1, OR_PURP_CHILD = 2, OR_PURP_ANNIH = 3,
 /* per-material table arrays */
 enum { OR_T_COMPTON = 0, OR_T_PAIR, OR_T_MOLLER, OR_T_BREMS_EM, OR_T_S_EM, OR_T_R_EM,
        OR_T_BHABHA, OR_T_BREMS_EP, OR_T_S_EP, OR_T_R_EP, OR_NTAB };
-enum { OR_FIELD_HELIX = 0, OR_FIELD_RK4 = 1 };
+enum { OR_FIELD_HELIX = 0, OR_FIELD_RK4 = 1, OR_FIELD_RK45 = 2 };
+/* field maps: uniform B, or an analytic finite solenoid along z */
+enum { OR_MAP_UNIFORM = 0, OR_MAP_SOLENOID = 1 };
 
 #define OR_OUTSIDE (-1)
 
@@ -61,7 +63,10 @@ typedef struct {
     const int32_t* cell;            /* n_vol; -1 = not scored */
     double env[2];                  /* slabs: half-x, half-y; shells: half-z */
     double world[4];                /* slabs: half-x, half-y, z-lo, z-hi; shells: r, half-z */
-    double B[3];                    /* tesla */
+    double B[3];                    /* tesla; the solenoid's central field is B[2] */
+    int32_t field_map;              /* OR_MAP_* */
+    int32_t pad;
+    double sol[2];                  /* solenoid coil radius and half-length, cm */
 } or_geometry;
 
 typedef struct {
@@ -78,6 +83,9 @@ typedef struct {
     int64_t max_steps;              /* looper cap */
     int32_t fs_alias;               /* bit m set: model m samples from tables (OR_AL_*) */
     int32_t pad;
+    double rk_tol;                  /* RK45: allowed error per substep (see or_rk45_move) */
+    int32_t rk_max_sub;             /* RK45: substep attempts per step before it is cut short */
+    int32_t pad2;
 } or_config;
 
 /* Histogram of escaping particles (single-slab observables, Sec. 4):
@@ -125,7 +133,7 @@ enum { OR_C_STEPS_G = 0, OR_C_STEPS_EM, OR_C_STEPS_EP,
        OR_C_TRACKS_G, OR_C_TRACKS_EM, OR_C_TRACKS_EP,
        OR_C_PROC0,                      /* OR_NPROC interaction counters */
        OR_C_ESCAPED = OR_C_PROC0 + OR_NPROC, OR_C_KILLED, OR_C_REJ_EXHAUSTED,
-       OR_C_TRACE_DROPPED, OR_NCOUNT };
+       OR_C_TRACE_DROPPED, OR_C_RK_SUB, OR_C_RK_REJ, OR_NCOUNT };
 
 /* ledger columns per event */
 enum { OR_L_ESCAPED = 0, OR_L_KILLED, OR_L_NPAIR, OR_L_NANNIH, OR_NLEDGER };
@@ -201,6 +209,30 @@ double or_safety(int32_t vol, const double pos[3]);
 void or_helix_move(int32_t type, double ekin, const double B[3], double s, double pos[3], double dir[3]);
 void or_rk4_move(int32_t type, double ekin, const double B[3], double s, int32_t nsub,
                  double pos[3], double dir[3]);
+
+/* A magnetic field: uniform B, or a finite solenoid of coil radius sol[0]
+ * and half-length sol[1] centred on the origin along z with central field
+ * B[2] (axial field of a uniform current sheet, extended off the axis to
+ * second order in r). */
+typedef struct {
+    int32_t map;                    /* OR_MAP_* */
+    int32_t pad;
+    double B[3];
+    double sol[2];
+} or_field;
+void or_field_eval(const or_field* f, const double x[3], double B[3]);
+/* classic RK4 with the field evaluated at every stage point */
+void or_rk4_field_move(int32_t type, double ekin, const or_field* f, double s, int32_t nsub,
+                       double pos[3], double dir[3]);
+/* Adaptive Dormand-Prince 5(4) over a path length s (see or_sample.c for the
+ * error measure and the step-size rule).  Returns the accepted substeps;
+ * *n_rej gets the rejected ones and *s_done the length integrated, which is
+ * below s only when max_sub attempts ran out. */
+int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, double tol,
+                     int32_t max_sub, double pos[3], double dir[3], double* s_done, int32_t* n_rej);
+/* the Dormand-Prince 5(4) coefficients: a[7*7] (row i, column j < i), the
+ * 5th-order weights b[7], the embedded 4th-order weights bh[7], nodes c[7] */
+void or_dp45_tableau(double* a, double* b, double* bh, double* c);
 double or_highland(int32_t m, double ekin, double s);
 void or_rotate(double dir[3], double cos_t, double sin_t, double phi);
 
