@@ -3,7 +3,8 @@
  *
  * The library transports electrons, positrons and photons through a layered
  * detector (a 1-D stack of slabs or cylindrical shells inside an envelope inside
- * a vacuum world, optionally in a uniform magnetic field) and scores the energy
+ * a vacuum world, optionally in a magnetic field: uniform, or the map of a finite
+ * solenoid) and scores the energy
  * each event deposits in each cell.  It is the data-parallel hot path of the
  * GeantV method (arXiv 2005.00949): instead of following one track at a time,
  * every stage of a step runs over whole track populations (Sec. 2, "algorithm-
@@ -47,7 +48,29 @@ typedef enum {
 enum { GV_AXIS_Z_SLABS = 0, GV_AXIS_R_SHELLS = 1 };
 enum { GV_DRIVER_PLAIN = 0, GV_DRIVER_BATCHED = 1 };
 enum { GV_P64 = 0, GV_PMIX = 1 };
-enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1 };
+/* Integration of charged tracks in the field (Sec. 3.6).  HELIX: closed-form
+ * helix in the field at the step's start point (exact in a uniform field).
+ * RK4: classic Runge-Kutta, ceil(s / (rk_frac * radius)) substeps, the field
+ * taken at every stage point.  RK45: adaptive Dormand-Prince 5(4) with first-
+ * same-as-last; a substep of length h has the error
+ *   err = max(max_a |sum_j e_j kx_j[a]|, max_a |h sum_j e_j ku_j[a]|)
+ * (e = 5th- minus 4th-order weights, kx / ku the position / direction stage
+ * derivatives): the position error per unit length and the direction error.
+ * A substep is accepted when err <= rk_tol.  The first attempt is
+ * h = min(s, 0.9 (rk_tol / K)^(1/4) / |du/ds|), K = 8.1e-4 being the pair's
+ * error constant on circular motion; then h is scaled by
+ * clamp(0.9 (rk_tol / err)^(1/5), 0.2, 5) after an accepted substep and by
+ * max(0.9 (rk_tol / err)^(1/5), 0.2) after a rejected one, and never passes
+ * the end.  After rk_max_substeps attempts the step ends where integration
+ * stopped. */
+enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1, GV_FIELD_RK45 = 2 };
+/* Field maps.  UNIFORM: B everywhere.  SOLENOID: a finite solenoid along z
+ * centred on the origin, coil radius sol_cm[0], half-length sol_cm[1],
+ * central field B[2] (B[0] = B[1] = 0): on the axis the field of a uniform
+ * current sheet, g(z) = B[2] f(z) / f(0) with
+ * f(z) = (z+L)/sqrt(R^2+(z+L)^2) - (z-L)/sqrt(R^2+(z-L)^2); off the axis
+ * B_r = -(r/2) g'(z), B_z = g(z) - (r^2/4) g''(z). */
+enum { GV_MAP_UNIFORM = 0, GV_MAP_SOLENOID = 1 };
 /* Order of tracks in the batched driver's queues between step launches.
  * ARRIVAL: each basket reserves its output range when it finishes (one
  * atomic add per queue), so queue order across baskets follows completion
@@ -105,7 +128,10 @@ typedef struct {
     const int32_t* cell;            /* n_vol */
     double env[2];
     double world[4];
-    double B[3];                    /* uniform field, tesla */
+    double B[3];                    /* field, tesla (see field_map) */
+    int32_t field_map;              /* GV_MAP_UNIFORM or GV_MAP_SOLENOID */
+    int32_t reserved;               /* must be 0 */
+    double sol_cm[2];               /* solenoid coil radius and half-length, > 0 for SOLENOID */
 } gv_geometry;
 
 /* Table grid and thresholds from which gv_init builds, on the device, the
@@ -147,7 +173,7 @@ typedef struct {
                                        size class), otherwise they take the defaults
                                        256 / 4 / 4 */
     int32_t graph_steps;            /* step launches per captured graph, 0 = default */
-    int32_t field_method;           /* GV_FIELD_HELIX or GV_FIELD_RK4 */
+    int32_t field_method;           /* GV_FIELD_HELIX, GV_FIELD_RK4 or GV_FIELD_RK45 */
     int32_t edep_on_device;         /* edep_out of gv_transport is a device pointer */
     int64_t max_steps_per_track;    /* looper cap, default 2^20 (< 2^24) */
     int64_t capacity;               /* track slots per particle-type queue, 0 = default */
@@ -162,6 +188,9 @@ typedef struct {
     int32_t fs_alias;               /* bit m set (m = GV_FS_*): model m samples its final state
                                        from tables instead of by rejection; default 0 */
     int32_t reserved2;              /* must be 0 */
+    double rk_tol;                  /* RK45 error tolerance, 0 = default 1e-6 */
+    int32_t rk_max_substeps;        /* RK45 attempts per step, 1..2^20, 0 = default 10000 */
+    int32_t reserved3;              /* must be 0 */
 } gv_config;
 
 /* Counters of the last gv_transport. */
@@ -196,6 +225,12 @@ typedef struct {
     int32_t reserved;
     double tail_kernel_ms;          /* part of kernel_ms spent after the population peaked and
                                        fell below the tail threshold (batched driver) */
+    int64_t rk_substeps;            /* RK45: accepted substeps */
+    int64_t rk_rejected;            /* RK45: rejected attempts */
+    int64_t rk_lane_slots;          /* RK45: for every group of lanes of one wavefront that
+                                       integrate together, (lanes) x (most attempts among
+                                       them); 1 - (substeps + rejected) / lane_slots is the
+                                       fraction of idle lanes in the integration loop */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

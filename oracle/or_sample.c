@@ -187,10 +187,18 @@ static void dp_deriv(const or_field* f, double kq, const double y[6], double k[6
  *   error measure of a substep of length h, with e = b - bh:
  *     err = max( max_a |sum_j e_j kx_j[a]|,  max_a |h sum_j e_j ku_j[a]| )
  *   (position error per unit length, and direction error); accepted when
- *   err <= tol.  The first attempt covers the whole remaining length; a
- *   rejected attempt halves h, an accepted one with err <= tol/32 doubles
- *   the next h; h never passes the end of the interval.  Stops after
- *   max_sub attempts.  Sums over stages run in stage order. */
+ *   err <= tol.
+ *   first attempt: h = min(s, theta / |du/ds|) with theta =
+ *   0.8 (tol / RK45_K)^(1/4), where RK45_K is the constant of this pair's
+ *   error measure on circular motion (err ~ RK45_K (h |du/ds|)^4 for small
+ *   turning angles);
+ *   next h: halved after a rejected attempt, doubled after an accepted
+ *   substep with err <= tol/16 (the position part scales as h^4), never past
+ *   the end of the interval.  Powers of two keep every substep length an
+ *   exact function of s and theta, so any two IEEE implementations take the
+ *   same substeps.  Stops after max_sub attempts.  Sums over stages run in
+ *   stage order. */
+#define RK45_K 8.1e-4
 int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, double tol,
                      int32_t max_sub, double pos[3], double dir[3], double* s_done, int32_t* n_rej)
 {
@@ -202,6 +210,13 @@ int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, dou
     *s_done = 0.0;
     *n_rej = 0;
     if (!(s > 0.0)) return 0;
+    {
+        double k0[6];
+        dp_deriv(f, kq, y, k0);
+        double w = sqrt(k0[3] * k0[3] + k0[4] * k0[4] + k0[5] * k0[5]);
+        double theta = 0.8 * sqrt(sqrt(tol / RK45_K));
+        if (h * w > theta) h = theta / w;
+    }
     while (acc + rej < max_sub) {
         double rem = s - done;
         int last = h >= rem;
@@ -232,7 +247,7 @@ int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, dou
                 break;
             }
             done += h;
-            if (err <= tol * (1.0 / 32.0)) h *= 2.0;
+            if (err <= tol * (1.0 / 16.0)) h *= 2.0;
         } else {
             ++rej;
             h *= 0.5;

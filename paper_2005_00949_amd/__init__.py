@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "GV_OK", 1: "GV_E_INVALID_ARG", 2: "GV_E_GEOMETRY", 3: "GV_E_
                 5: "GV_E_NOT_INIT", 6: "GV_E_CAPACITY", 7: "GV_E_STATE"}
 DRIVER_PLAIN, DRIVER_BATCHED = 0, 1
 P64, PMIX = 0, 1
-FIELD_HELIX, FIELD_RK4 = 0, 1
+FIELD_HELIX, FIELD_RK4, FIELD_RK45 = 0, 1, 2
+MAP_UNIFORM, MAP_SOLENOID = 0, 1
 ORDER_ARRIVAL, ORDER_STABLE = 0, 1
 DEPOSIT_FLOAT, DEPOSIT_FIXED = 0, 1
 FS_COMPTON, FS_PAIR, FS_BREMS, FS_MOLLER, FS_BHABHA = 0, 1, 2, 3, 4
@@ -46,7 +47,8 @@ class Material(C.Structure):
 class Geometry(C.Structure):
     _fields_ = [("axis", C.c_int32), ("n_vol", C.c_int32), ("bounds", C.POINTER(C.c_double)),
                 ("material", C.POINTER(C.c_int32)), ("cell", C.POINTER(C.c_int32)),
-                ("env", C.c_double * 2), ("world", C.c_double * 4), ("B", C.c_double * 3)]
+                ("env", C.c_double * 2), ("world", C.c_double * 4), ("B", C.c_double * 3),
+                ("field_map", C.c_int32), ("reserved", C.c_int32), ("sol_cm", C.c_double * 2)]
 
 
 class Tables(C.Structure):
@@ -63,7 +65,8 @@ class Config(C.Structure):
                 ("max_events_in_flight", C.c_int64), ("chord_tol_cm", C.c_double),
                 ("push_cm", C.c_double), ("rk_frac", C.c_double), ("hip_stream", C.c_void_p),
                 ("trace_cap", C.c_int64), ("queue_order", C.c_int32), ("deposit_mode", C.c_int32),
-                ("fs_alias", C.c_int32), ("reserved2", C.c_int32)]
+                ("fs_alias", C.c_int32), ("reserved2", C.c_int32),
+                ("rk_tol", C.c_double), ("rk_max_substeps", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -79,7 +82,8 @@ class Stats(C.Structure):
                 ("occupancy", C.c_int32), ("inner_steps", C.c_int32), ("graph_steps", C.c_int32),
                 ("capacity", C.c_int64), ("state_bytes", C.c_double), ("autotune_ms", C.c_double),
                 ("tuned", C.c_int32), ("queue_order", C.c_int32), ("reserved", C.c_int32),
-                ("tail_kernel_ms", C.c_double)]
+                ("tail_kernel_ms", C.c_double),
+                ("rk_substeps", C.c_int64), ("rk_rejected", C.c_int64), ("rk_lane_slots", C.c_int64)]
 
 
 class DebugIO(C.Structure):
@@ -174,6 +178,9 @@ class Engine:
             g.world[i] = float(geom["world"][i])
         for i in range(3):
             g.B[i] = float(geom["B"][i])
+        g.field_map = int(geom.get("field_map", MAP_UNIFORM))
+        sol = geom.get("sol", (0.0, 0.0))
+        g.sol_cm[0], g.sol_cm[1] = float(sol[0]), float(sol[1])
         t = Tables(ts["e_min"], ts["bins_per_decade"], ts["n_nodes"], 0, ts["t_cut"], ts["k_cut"],
                    ts["t_track"])
         _check(self.lib.gv_init(arr, len(mats), C.byref(g), C.byref(t)))
@@ -185,7 +192,8 @@ class Engine:
                            graph_steps=0, field_method=FIELD_HELIX, edep_on_device=0,
                            max_steps_per_track=1 << 20, capacity=0, max_events_in_flight=0,
                            chord_tol_cm=1e-3, push_cm=1e-7, rk_frac=0.05, hip_stream=None, trace_cap=0,
-                           queue_order=ORDER_ARRIVAL, deposit_mode=DEPOSIT_FLOAT, fs_alias=0)
+                           queue_order=ORDER_ARRIVAL, deposit_mode=DEPOSIT_FLOAT, fs_alias=0,
+                           rk_tol=0.0, rk_max_substeps=0)
         self.configure(**config)
 
     def configure(self, **kw):

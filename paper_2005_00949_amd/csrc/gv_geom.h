@@ -40,6 +40,9 @@ struct DevGeom {
     double Bmag;
     double Bhat[3];               // B / |B| (0 when there is no field)
     double kB;                    // kKB * |B|: curvature per unit momentum, 1/(cm MeV)
+    int field_map;                // 0 uniform B, 1 finite solenoid along z (central field B[2])
+    int pad_map;
+    double sol_R2, sol_L, sol_c;  // solenoid: coil radius^2, half-length, B0 / f(0)
     double bounds[GV_MAX_VOLS + 1];
     int vmat[GV_MAX_VOLS];
     int vcell[GV_MAX_VOLS];

@@ -84,7 +84,12 @@ __device__ __forceinline__ void store_child(const Soa<P>& q, size_t i, const Tra
 
 // global counters (gv_stats)
 enum : int { kCSteps = 0, kCTracks = 3, kCProc = 6, kCEscaped = 14, kCKilled = 15, kCRej = 16, kCLoads = 17,
-             kCStores = 18, kNCount = 19 };
+             kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kNCount = 22 };
+
+// per-lane sums of the adaptive-integration tallies over one launch
+struct RkSum {
+    uint32_t acc, rej, slots;
+};
 
 struct Sinks {
     double* edep;                 // [event][cell]
@@ -528,7 +533,7 @@ __global__ void k_dbg_step(DbgStepIO io, long long n, uint64_t seed, TabView<typ
     t.nstep = io.nstep[i];
     t.vol = locate(c_geom, t.x);
     StepOut<R> o;
-    step_track(c, t, o);
+    step_track<P, true>(c, t, o);
     for (int a = 0; a < 3; ++a) {
         io.pos[3 * i + a] = t.x[a];
         io.dir[3 * i + a] = (double)t.u[a];
@@ -707,11 +712,11 @@ __device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[
 // photon and charged-particle step paths are specialised): step each track up
 // to `inner` times in registers, stopping at its first secondary or its end;
 // then compact survivor + secondaries into the output queues.
-template <class P, int TY, int BLOCK, bool STABLE, class R = typename P::R>
+template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, class R = typename P::R>
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
-                                              uint32_t& loads, uint32_t& stores, uint32_t n_chunks)
+                                              uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -729,8 +734,13 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         int acc_vol = t.vol;
         for (int k = 0; k < inner; ++k) {
             const uint32_t ns = t.nstep;
-            step_track(c, t, o);
+            step_track<P, INTEG>(c, t, o);
             steps_here += o.did_step;
+            if (TY != kGamma) {
+                rks.acc += (uint32_t)o.rk.acc;
+                rks.rej += (uint32_t)o.rk.rej;
+                rks.slots += (uint32_t)o.rk.iters;
+            }
             if (o.vol_pre != acc_vol) {
                 dep_add(dc, A.S, t.ev, acc_vol, acc);
                 acc.e = 0.0;
@@ -793,13 +803,17 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
     __syncthreads();
 }
 
-template <class P, int BLOCK, bool STABLE>
+// INTEG: field integrators compiled in (field_method RK4 / RK45); the helix
+// variant leaves them out and keeps its register budget.
+template <class P, int BLOCK, bool STABLE, bool INTEG>
 __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
 {
     __shared__ ScanShared<BLOCK> sh;
     __shared__ unsigned cnt_lds[kNCount];
+    __shared__ unsigned long long rk_lds[3];
     __shared__ DepCache dc;
     for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
+    if (threadIdx.x < 3) rk_lds[threadIdx.x] = 0ull;
     dep_clear<BLOCK>(dc);
 
     const int pin = A.parity;
@@ -824,6 +838,7 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
     uint32_t steps_g = 0, steps_e = 0, steps_p = 0;
     uint32_t loads = 0, stores = 0;
+    RkSum rks{0u, 0u, 0u};
     __syncthreads();
 
     for (;;) {
@@ -835,14 +850,14 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
         const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
-                process_chunk<P, kGamma, BLOCK, STABLE>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
-                                                loads, stores, n_chunks);
+                process_chunk<P, kGamma, BLOCK, STABLE, INTEG>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
+                                                loads, stores, n_chunks, rks);
             else if (chunk < c0 + c1)
-                process_chunk<P, kElectron, BLOCK, STABLE>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
-                                                   steps_e, loads, stores, n_chunks);
+                process_chunk<P, kElectron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
+                                                   steps_e, loads, stores, n_chunks, rks);
             else
-                process_chunk<P, kPositron, BLOCK, STABLE>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
-                                                   cnt_lds, steps_p, loads, stores, n_chunks);
+                process_chunk<P, kPositron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
+                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);
@@ -850,9 +865,15 @@ __global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
     atomicAdd(&cnt_lds[kCSteps + kPositron], steps_p);
     atomicAdd(&cnt_lds[kCLoads], loads);
     atomicAdd(&cnt_lds[kCStores], stores);
+    if (rks.slots) {
+        atomicAdd(&rk_lds[0], (unsigned long long)rks.acc);
+        atomicAdd(&rk_lds[1], (unsigned long long)rks.rej);
+        atomicAdd(&rk_lds[2], (unsigned long long)rks.slots);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < kNCount; i += BLOCK)
         if (cnt_lds[i]) atomicAdd(&A.S.counters[i], (unsigned long long)cnt_lds[i]);
+    if (threadIdx.x < 3 && rk_lds[threadIdx.x]) atomicAdd(&A.S.counters[kCRkSub + threadIdx.x], rk_lds[threadIdx.x]);
     finish_launch(A.ctrl, pin, participants);
 }
 
@@ -926,8 +947,13 @@ __global__ void k_plain_move(PlainArgs A)
     const Limits<double> L = A.L[i];
     const Geo G = A.G[i];
     Prop<double> pr;
-    stage_move(c, t, L, G, pr);
+    stage_move<P64, true>(c, t, L, G, pr);
     A.pr[i] = pr;
+    if (pr.rk.iters) {
+        atomicAdd(&A.S.counters[kCRkSub], (unsigned long long)pr.rk.acc);
+        atomicAdd(&A.S.counters[kCRkRej], (unsigned long long)pr.rk.rej);
+        atomicAdd(&A.S.counters[kCRkSlots], (unsigned long long)pr.rk.iters);
+    }
     store_track(A.pool, (size_t)i, t);
     StepOut<double>& o = A.o[i];
     o.did_step = 1;

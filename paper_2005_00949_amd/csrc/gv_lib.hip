@@ -129,14 +129,14 @@ struct GraphKey {
     const void* edep = nullptr;
     const void* trace = nullptr;
     long long trace_cap = 0;
-    int order = -1, fixed = -1;
+    int order = -1, fixed = -1, field = -1;
     int grid = 0, tail_grid = 0, tail_K = 0;
     bool operator==(const GraphKey& o) const
     {
         return prec == o.prec && block == o.block && chunks == o.chunks && inner_bulk == o.inner_bulk &&
                inner_tail == o.inner_tail && K == o.K && tail == o.tail && cap == o.cap && qblock == o.qblock &&
                edep == o.edep && trace == o.trace && trace_cap == o.trace_cap && order == o.order && fixed == o.fixed &&
-               grid == o.grid && tail_grid == o.tail_grid && tail_K == o.tail_K;
+               field == o.field && grid == o.grid && tail_grid == o.tail_grid && tail_K == o.tail_K;
     }
 };
 
@@ -231,6 +231,9 @@ gv_config default_config()
     c.deposit_mode = GV_DEPOSIT_FLOAT;
     c.fs_alias = 0;
     c.reserved2 = 0;
+    c.rk_tol = 0.0;
+    c.rk_max_substeps = 0;
+    c.reserved3 = 0;
     return c;
 }
 
@@ -435,7 +438,10 @@ int validate_config(const gv_config& c)
     if (c.inner_steps < 0 || c.inner_steps > 1 << 16) return fail(GV_E_INVALID_ARG, "inner_steps");
     if (c.graph_steps < 0 || c.graph_steps > 4096 || (c.graph_steps & 1))
         return fail(GV_E_INVALID_ARG, "graph_steps must be 0 or an even number <= 4096");
-    if (c.field_method != GV_FIELD_HELIX && c.field_method != GV_FIELD_RK4) return fail(GV_E_INVALID_ARG, "field_method");
+    if (c.field_method != GV_FIELD_HELIX && c.field_method != GV_FIELD_RK4 && c.field_method != GV_FIELD_RK45)
+        return fail(GV_E_INVALID_ARG, "field_method");
+    if (!(c.rk_tol >= 0.0) || !(c.rk_tol < 1.0) || c.rk_max_substeps < 0 || c.rk_max_substeps > (1 << 20))
+        return fail(GV_E_INVALID_ARG, "rk_tol must be in [0, 1), rk_max_substeps in [0, 2^20]");
     if (c.max_steps_per_track < 1 || c.max_steps_per_track >= (1 << 24))
         return fail(GV_E_INVALID_ARG, "max_steps_per_track must be in [1, 2^24)");
     if (c.capacity < 0 || c.capacity > (int64_t)1 << 31) return fail(GV_E_INVALID_ARG, "capacity");
@@ -448,7 +454,7 @@ int validate_config(const gv_config& c)
     if (c.deposit_mode != GV_DEPOSIT_FLOAT && c.deposit_mode != GV_DEPOSIT_FIXED)
         return fail(GV_E_INVALID_ARG, "deposit_mode");
     if (c.fs_alias < 0 || c.fs_alias >= (1 << kAlNMod)) return fail(GV_E_INVALID_ARG, "fs_alias");
-    if (c.reserved2 != 0) return fail(GV_E_INVALID_ARG, "reserved field must be 0");
+    if (c.reserved2 != 0 || c.reserved3 != 0) return fail(GV_E_INVALID_ARG, "reserved field must be 0");
     return GV_OK;
 }
 
@@ -458,6 +464,8 @@ int apply_run_params()
     L.phys.chord_tol = L.cfg.chord_tol_cm;
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
+    L.phys.rk_tol = L.cfg.rk_tol > 0.0 ? L.cfg.rk_tol : 1.0e-6;
+    L.phys.rk_max_sub = L.cfg.rk_max_substeps > 0 ? L.cfg.rk_max_substeps : 10000;
     L.phys.max_steps = L.cfg.max_steps_per_track;
     L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_phys), &L.phys, sizeof(DevPhys), 0, hipMemcpyHostToDevice, stream()));
@@ -622,19 +630,26 @@ int ingest(size_t b, size_t e, Soa<P> q[3], uint32_t counts[3], size_t cap, bool
     return GV_OK;
 }
 
-template <class P, int BLOCK> void launch_step(const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
+template <class P, int BLOCK, bool INTEG> void launch_step(const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
 {
-    if (stable) k_step_batched<P, BLOCK, true><<<grid, BLOCK, 0, s>>>(A);
-    else k_step_batched<P, BLOCK, false><<<grid, BLOCK, 0, s>>>(A);
+    if (stable) k_step_batched<P, BLOCK, true, INTEG><<<grid, BLOCK, 0, s>>>(A);
+    else k_step_batched<P, BLOCK, false, INTEG><<<grid, BLOCK, 0, s>>>(A);
+}
+
+template <class P, bool INTEG>
+void launch_step_block(int block, const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
+{
+    switch (block) {
+    case 64: launch_step<P, 64, INTEG>(A, grid, stable, s); break;
+    case 128: launch_step<P, 128, INTEG>(A, grid, stable, s); break;
+    default: launch_step<P, 256, INTEG>(A, grid, stable, s); break;
+    }
 }
 
 template <class P> void launch_step_dispatch(int block, const BatchArgs<P>& A, int grid, bool stable, hipStream_t s)
 {
-    switch (block) {
-    case 64: launch_step<P, 64>(A, grid, stable, s); break;
-    case 128: launch_step<P, 128>(A, grid, stable, s); break;
-    default: launch_step<P, 256>(A, grid, stable, s); break;
-    }
+    if (L.cfg.field_method != GV_FIELD_HELIX) launch_step_block<P, true>(block, A, grid, stable, s);
+    else launch_step_block<P, false>(block, A, grid, stable, s);
 }
 
 template <class P> QueueMem<P>& batch_queues();
@@ -708,6 +723,7 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     key.trace_cap = L.cfg.trace_cap;
     key.order = L.cfg.queue_order;
     key.fixed = L.cfg.deposit_mode;
+    key.field = L.cfg.field_method;
     key.grid = tu.occupancy * L.n_cu;
     key.tail_grid = tu.tail_grid;
     key.tail_K = tu.tail_K;
@@ -1059,6 +1075,21 @@ int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom, co
     g.Bmag = std::sqrt(g.B[0] * g.B[0] + g.B[1] * g.B[1] + g.B[2] * g.B[2]);
     for (int i = 0; i < 3; ++i) g.Bhat[i] = g.Bmag > 0.0 ? g.B[i] / g.Bmag : 0.0;
     g.kB = kKB * g.Bmag;
+    if (geom->reserved != 0) return fail(GV_E_GEOMETRY, "reserved field must be 0");
+    if (geom->field_map != GV_MAP_UNIFORM && geom->field_map != GV_MAP_SOLENOID) return fail(GV_E_GEOMETRY, "field_map");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(g.B[i])) return fail(GV_E_GEOMETRY, "non-finite field");
+    g.field_map = geom->field_map;
+    if (g.field_map == GV_MAP_SOLENOID) {
+        const double R = geom->sol_cm[0], Lh = geom->sol_cm[1];
+        if (g.B[0] != 0.0 || g.B[1] != 0.0 || !(R > 0.0) || !(Lh > 0.0) || !std::isfinite(R) || !std::isfinite(Lh))
+            return fail(GV_E_GEOMETRY, "solenoid needs B along z and a positive finite radius and half-length");
+        // B0 / f(0) with f(0) = 2L / sqrt(R^2 + L^2)
+        g.sol_R2 = R * R;
+        g.sol_L = Lh;
+        const double f0 = 2.0 * Lh / std::sqrt(g.sol_R2 + Lh * Lh);
+        g.sol_c = g.B[2] / f0;
+    }
     if (g.axis == GV_AXIS_Z_SLABS) {
         if (!(g.env[0] > 0 && g.env[1] > 0 && g.world[0] >= g.env[0] && g.world[1] >= g.env[1] &&
               g.world[2] <= g.bounds[0] && g.world[3] >= g.bounds[g.n_vol]))
@@ -1104,6 +1135,8 @@ int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom, co
     L.phys.chord_tol = L.cfg.chord_tol_cm;
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
+    L.phys.rk_tol = 1.0e-6;
+    L.phys.rk_max_sub = 10000;
     L.phys.max_steps = L.cfg.max_steps_per_track;
     L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_geom), &L.geom, sizeof(DevGeom), 0, hipMemcpyHostToDevice, stream()));
@@ -1249,6 +1282,9 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     L.stats.escaped = (int64_t)cnt[kCEscaped];
     L.stats.killed = (int64_t)cnt[kCKilled];
     L.stats.rejection_exhausted = (int64_t)cnt[kCRej];
+    L.stats.rk_substeps = (int64_t)cnt[kCRkSub];
+    L.stats.rk_rejected = (int64_t)cnt[kCRkRej];
+    L.stats.rk_lane_slots = (int64_t)cnt[kCRkSlots];
     L.stats.trace_records = (int64_t)std::min<unsigned long long>(tn, (unsigned long long)L.cfg.trace_cap);
     L.stats.e_in = L.e_in;
     double ed = 0.0, es = 0.0, ek = 0.0, np_ = 0.0, na = 0.0;

@@ -23,6 +23,9 @@ struct DevPhys {
     double e_min, bpd, log10_emin;
     double t_cut, k_cut, t_track;
     double chord_tol, push, rk_frac;
+    double rk_tol;           // RK45 error tolerance
+    int rk_max_sub;          // RK45 attempts per step
+    int pad3;
     long long max_steps;
     // final-state tables (alias sampling): model m uses them when bit m of
     // fs_alias is set; records per (model, node) as built by k_build_alias

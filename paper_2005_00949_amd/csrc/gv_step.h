@@ -7,7 +7,8 @@
 //   GeomQuery       (stage_geom)      distance to boundary, next volume, safety
 //   Propagation     (stage_move)      straight line, or in a field the rule of
 //                                     Sec. 3.4: min(min(phys, boundary),
-//                                     max(field, safety)), helix/RK4, relocate
+//                                     max(field, safety)), helix/RK4/RK45
+//                                     (Sec. 3.6), relocate
 //   PostPropagation (stage_msc)       Highland multiple scattering
 //   AlongStepAction (stage_eloss)     restricted continuous loss, deposit
 //   PostStepActions + SteppingActions (stage_finish)  discrete interaction at
@@ -18,6 +19,7 @@
 #include "gv_common.h"
 #include "gv_geom.h"
 #include "gv_physics.h"
+#include "gv_field.h"
 
 namespace gv {
 
@@ -42,6 +44,7 @@ template <class R> struct Child {
 
 // per-step outputs that leave the track itself
 template <class R> struct StepOut {
+    RkTally rk;         // adaptive integration work of this step (RK45 only)
     int status;         // kAlive / kDead / kEscaped / kKilled
     int did_step;       // a propagation happened (counts as a step)
     int lim;
@@ -78,6 +81,7 @@ template <class R> struct Prop {
     R T_pre;
     int lim;
     int crossed;
+    RkTally rk;
 };
 
 template <class P> struct Ctx {
@@ -93,6 +97,9 @@ template <class R> __device__ __forceinline__ R big_len() { return (R)1.0e30; }
 template <class P, class R = typename P::R>
 __device__ __forceinline__ void init_out(const Track<P>& t, StepOut<R>& o)
 {
+    o.rk.acc = 0;
+    o.rk.rej = 0;
+    o.rk.iters = 0;
     o.status = kAlive;
     o.did_step = 0;
     o.lim = -1;
@@ -224,7 +231,10 @@ __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 }
 
 // ---- Propagation --------------------------------------------------------
-template <class P, class R = typename P::R>
+// INTEG = false compiles the straight line and the helix only (field_method
+// HELIX); INTEG = true adds the RK4 and RK45 integrators, which run in double
+// in both precision policies.
+template <class P, bool INTEG, class R = typename P::R>
 __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
 #pragma clang fp contract(off)
@@ -234,7 +244,22 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     const double s_lim = fmin(s_phys, s_eloss);
     pr.T_pre = t.T;
     pr.crossed = 0;
-    if (t.type == kGamma || g.Bmag == 0.0) {
+    pr.rk.acc = 0;
+    pr.rk.rej = 0;
+    pr.rk.iters = 0;
+    // the field at the pre-step point: its direction and kKB |B|
+    double Bm = g.Bmag, kB = g.kB;
+    double bh[3] = {g.Bhat[0], g.Bhat[1], g.Bhat[2]};
+    if (t.type != kGamma && g.field_map == kMapSolenoid) {
+        // in double: the helix phase is kB s / p (see rk4_map_move)
+        double Bd[3];
+        field_at<double>(g, t.x, Bd);
+        Bm = sqrt(Bd[0] * Bd[0] + Bd[1] * Bd[1] + Bd[2] * Bd[2]);
+        kB = kKB * Bm;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bh[a] = Bm > 0.0 ? Bd[a] / Bm : 0.0;
+    }
+    if (t.type == kGamma || Bm == 0.0) {
         if (G.d_bnd <= s_lim) {
             pr.s = G.d_bnd;
             pr.lim = kLimGeom;
@@ -253,15 +278,15 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
         }
         return;
     }
-    // charged particle in a uniform field
+    // charged particle in a field
     const R p = m_sqrt(t.T * (t.T + (R)(2.0 * kMe)));
     // sine of the pitch angle from |u x b| (no cancellation near 0 or pi)
-    const R bx = (R)g.Bhat[0], by = (R)g.Bhat[1], bz = (R)g.Bhat[2];
+    const R bx = (R)bh[0], by = (R)bh[1], bz = (R)bh[2];
     const R cx = t.u[1] * bz - t.u[2] * by, cy = t.u[2] * bx - t.u[0] * bz, cz = t.u[0] * by - t.u[1] * bx;
     const R sin2 = cx * cx + cy * cy + cz * cz;
     double rcurv = kInf, dfield = kInf;
     if (sin2 > (R)0) {
-        const R rc = p / ((R)g.kB * m_sqrt(sin2));
+        const R rc = p / ((R)kB * m_sqrt(sin2));
         rcurv = (double)rc;
         dfield = (double)m_sqrt((R)2 * rc * (R)c.ph->chord_tol);
     }
@@ -275,12 +300,26 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
         pr.lim = kLimField;
     }
     if (pr.lim == kLimGeom) pr.s += c.ph->push;
-    if (c.ph->field_method == 1) {
-        double nsub = rcurv < kInf ? ceil(pr.s / (c.ph->rk_frac * rcurv)) : 1.0;
-        nsub = nsub < 1.0 ? 1.0 : (nsub > 100000.0 ? 100000.0 : nsub);
-        rk4_move<R>(t.type, t.T, g.B, pr.s, (int)nsub, t.x, t.u);
+    if (INTEG && c.ph->field_method != kFieldHelix) {
+        double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
+        const double T = (double)t.T;
+        if (c.ph->field_method == kFieldRk45) {
+            const double s_done = rk45_move(g, t.type, T, pr.s, c.ph->rk_tol, c.ph->rk_max_sub, t.x, ud, pr.rk);
+            if (s_done < pr.s) {  // attempts ran out: the step ends where integration stopped
+                pr.s = s_done;
+                pr.lim = kLimField;
+            }
+        } else {
+            double nsub = rcurv < kInf ? ceil(pr.s / (c.ph->rk_frac * rcurv)) : 1.0;
+            nsub = nsub < 1.0 ? 1.0 : (nsub > 100000.0 ? 100000.0 : nsub);
+            if (g.field_map == kMapSolenoid) rk4_map_move(g, t.type, T, pr.s, (int)nsub, t.x, ud);
+            else rk4_move<double>(t.type, T, g.B, pr.s, (int)nsub, t.x, ud);
+        }
+        t.u[0] = (R)ud[0];
+        t.u[1] = (R)ud[1];
+        t.u[2] = (R)ud[2];
     } else {
-        helix_move<R>(t.type, t.T, g.Bhat, g.kB, pr.s, t.x, t.u);
+        helix_move<R>(t.type, t.T, bh, kB, pr.s, t.x, t.u);
     }
     const int nv = locate(g, t.x);
     if (nv != t.vol) {
@@ -470,7 +509,7 @@ __device__ inline void stage_finish(const Ctx<P>& c, Track<P>& t, const Limits<R
 }
 
 // ---- the whole step in registers ----------------------------------------
-template <class P, class R = typename P::R>
+template <class P, bool INTEG, class R = typename P::R>
 __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
 {
     init_out(t, o);
@@ -480,13 +519,14 @@ __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
     Geo G;
     stage_geom(c, t, G);
     Prop<R> pr;
-    stage_move(c, t, L, G, pr);
+    stage_move<P, INTEG>(c, t, L, G, pr);
     o.did_step = 1;
     o.s = pr.s;
     o.lim = pr.lim;
     o.s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
     o.d_bnd = G.d_bnd;
     o.safety = G.safety;
+    o.rk = pr.rk;
     stage_msc(c, t, L, pr);
     const bool stopped = stage_eloss(c, t, L, pr, o);
     stage_finish(c, t, L, pr, stopped, o);

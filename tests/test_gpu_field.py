@@ -1,0 +1,168 @@
+"""Field integration on the GPU against the oracle (Sec. 3.6), through the C ABI.
+
+* One step of 200k random states in the uniform 4 T slab field and in the
+  solenoid map, for helix / RK4 / RK45: FP64 to 1e-12 with at most two
+  discrete flips, the mixed path to 1e-5 (flips and violations per 1e4).
+* Tiny showers in the solenoid map with RK45: every step record of the FP64
+  drivers equals the oracle's within the history tolerance, and the RK45
+  substep and rejection counts equal the oracle's (to one decision in 1e4).
+* Energy ledger closes with RK45 in every driver and precision; the idle-lane
+  statistic is consistent (lane slots >= attempts).
+* Per-layer deposits of the mixed batched path with RK45 in the map against
+  the oracle: paired test, 3 sigma and 0.5% on layers holding >= 1%.
+"""
+import numpy as np
+import pytest
+
+import gv_inputs
+import gvtest
+
+pytestmark = pytest.mark.gpu
+ME = 0.51099895
+
+
+@pytest.fixture(scope="module")
+def gv():
+    import paper_2005_00949_amd as gvlib
+    return gvlib
+
+
+GEOMS = {
+    "slab4T": lambda: gv_inputs.slab_calorimeter(50, (0.0, 4.0, 0.0)),
+    "barrelmap": lambda: gv_inputs.barrel(field_map=gv_inputs.MAP_SOLENOID),
+}
+
+
+@pytest.mark.parametrize("precision", ["p64", "pmix"])
+@pytest.mark.parametrize("case", ["slab4T_rk45", "barrelmap_helix", "barrelmap_rk4", "barrelmap_rk45"])
+def test_single_step_parity_field_methods(gv, oracle_mod, case, precision):
+    which, method = case.split("_")
+    fm = {"helix": gv.FIELD_HELIX, "rk4": gv.FIELD_RK4, "rk45": gv.FIELD_RK45}[method]
+    geom = GEOMS[which]()
+    orc = oracle_mod.Oracle(geom, run_spec={"field_method": fm})
+    eng = gv.Engine(geom, field_method=fm)
+    n = 200_000
+    st = gv_inputs.random_states(n, 41, geom)
+    p = gv.P64 if precision == "p64" else gv.PMIX
+    if p == gv.PMIX:
+        st["ekin"] = st["ekin"].astype(np.float32).astype(np.float64)
+        st["dir"] = st["dir"].astype(np.float32).astype(np.float64)
+    ref = orc.single_step(st, 0x5151)
+    got = eng.debug_step(st, 0x5151, precision=p)
+    flips, worst = gvtest.compare_steps(got, ref, st, 1e-12 if p == gv.P64 else 1e-5)
+    print(f"\n[{case} {precision}] flips {flips}/{n}; worst {worst}")
+    if p == gv.P64:
+        assert flips <= 2, worst
+        assert not any(k.endswith("_violations") for k in worst), worst
+    else:
+        assert flips <= n * 2e-4, worst
+        viol = {k: v for k, v in worst.items() if k.endswith("_violations")}
+        assert sum(viol.values()) <= n * 1e-4, worst
+
+
+def _trace_map(tr):
+    return {(int(r["event"]), int(r["tid"]), int(r["nstep"])): r for r in tr}
+
+
+def _compare_histories(got, ref):
+    g, r = _trace_map(got), _trace_map(ref)
+    missing, extra = set(r) - set(g), set(g) - set(r)
+    worst, bad = 0.0, 0
+    for k in set(r) & set(g):
+        a, b = g[k], r[k]
+        if (a["limiter"], a["vol_pre"], a["vol_post"], a["process"], a["n_children"], a["type"]) != \
+           (b["limiter"], b["vol_pre"], b["vol_post"], b["process"], b["n_children"], b["type"]):
+            bad += 1
+            continue
+        e_scale = max(abs(float(b["ekin"])) + abs(float(b["edep"])), 1e-3)
+        l_scale = max(float(np.max(np.abs(b["pos"]))), abs(float(b["step"])), 1.0)
+        for f, sc in (("pos", l_scale), ("dir", 1.0), ("ekin", e_scale), ("edep", e_scale), ("step", l_scale)):
+            worst = max(worst, float(np.max(np.abs(np.asarray(a[f]) - np.asarray(b[f]))) / sc))
+    return len(missing), len(extra), bad, worst
+
+
+@pytest.mark.parametrize("driver", ["plain", "batched4", "batched1_stable"])
+def test_rk45_histories_in_solenoid_fp64(gv, oracle_mod, driver):
+    geom = gv_inputs.barrel(field_map=gv_inputs.MAP_SOLENOID)
+    prim = gv_inputs.barrel_beam(4, 7, 2000.0)
+    seed = 0x45
+    orc = oracle_mod.Oracle(geom, run_spec={"field_method": oracle_mod.FIELD_RK45})
+    ref = orc.transport(prim, seed, trace_cap=2_000_000)
+    cfg = dict(precision=gv.P64, trace_cap=2_000_000, field_method=gv.FIELD_RK45)
+    if driver == "plain":
+        cfg["driver"] = gv.DRIVER_PLAIN
+    else:
+        cfg.update(driver=gv.DRIVER_BATCHED, basket=128, inner_steps=4 if driver == "batched4" else 1,
+                   queue_order=gv.ORDER_STABLE if driver.endswith("stable") else gv.ORDER_ARRIVAL)
+    eng = gv.Engine(geom, **cfg)
+    edep = eng.transport(prim, seed)
+    st = eng.stats()
+    got = eng.trace()
+    missing, extra, bad, worst = _compare_histories(got, ref["trace"])
+    n_ref = len(ref["trace"])
+    c = ref["counters"]
+    print(f"\n[barrel map RK45 {driver}] steps {n_ref}/{len(got)} missing {missing} extra {extra} "
+          f"discrete {bad} worst {worst:.2e}; substeps {st['rk_substeps']}/{c['rk_substeps']} "
+          f"rejected {st['rk_rejected']}/{c['rk_rejected']} lane slots {st['rk_lane_slots']}")
+    assert st["trace_records"] < 2_000_000
+    assert missing <= n_ref * 1e-3 and extra <= n_ref * 1e-3 and bad <= max(2, n_ref * 1e-3)
+    assert worst < 1e-6
+    assert np.allclose(edep, ref["edep"], rtol=1e-8, atol=1e-8 * max(1.0, ref["edep"].max()))
+    # the integrations take the same substeps, up to an accept decision that
+    # a ~1e-16 difference carried along the history can tip
+    tot = c["rk_substeps"] + c["rk_rejected"]
+    assert abs(st["rk_substeps"] - c["rk_substeps"]) <= max(2, tot * 1e-4)
+    assert abs(st["rk_rejected"] - c["rk_rejected"]) <= max(2, tot * 1e-4)
+    assert st["rk_substeps"] > 0
+    assert st["rk_lane_slots"] >= st["rk_substeps"] + st["rk_rejected"]
+
+
+@pytest.mark.parametrize("mode", ["plain64", "batch64", "batchmix"])
+def test_rk45_ledger_and_idle_lanes(gv, mode):
+    geom, prim, seed = gv_inputs.workload("c5m", 8)
+    cfg = {"plain64": dict(driver=gv.DRIVER_PLAIN, precision=gv.P64),
+           "batch64": dict(driver=gv.DRIVER_BATCHED, precision=gv.P64),
+           "batchmix": dict(driver=gv.DRIVER_BATCHED, precision=gv.PMIX)}[mode]
+    eng = gv.Engine(geom, field_method=gv.FIELD_RK45, **cfg)
+    edep = eng.transport(prim, seed)
+    L = eng.ledger()
+    Ein = np.bincount(prim["event"], weights=prim["ekin"])
+    lhs = Ein + 2 * ME * L[:, 3] - 2 * ME * L[:, 2]
+    rhs = edep.sum(1) + L[:, 0] + L[:, 1]
+    resid = float(np.max(np.abs(lhs - rhs) / lhs))
+    st = eng.stats()
+    att = st["rk_substeps"] + st["rk_rejected"]
+    idle = 1.0 - att / max(st["rk_lane_slots"], 1)
+    print(f"\n[c5m RK45 {mode}] ledger {resid:.1e}; substeps/charged step "
+          f"{st['rk_substeps'] / max(st['steps'][1] + st['steps'][2], 1):.2f}, rejected {st['rk_rejected']}, "
+          f"idle lanes {idle:.3f}")
+    assert resid < (1e-10 if mode != "batchmix" else 1e-5), resid
+    assert st["killed"] == 0
+    assert st["rk_substeps"] >= st["steps"][1] // 2
+    assert st["rk_lane_slots"] >= att and 0.0 <= idle < 1.0
+    # helix and RK4 leave the RK45 counters at zero
+    eng.configure(field_method=gv.FIELD_HELIX)
+    eng.transport(prim, seed)
+    assert eng.stats()["rk_lane_slots"] == 0
+
+
+def test_rk45_paired_layer_deposits_mixed_vs_oracle(gv, oracle_mod):
+    geom, prim, seed = gv_inputs.workload("c5m", 300)
+    prim = prim.copy()
+    prim["ekin"] = 2000.0
+    ref = oracle_mod.Oracle(geom, run_spec={"field_method": oracle_mod.FIELD_RK45}).transport(prim, seed)["edep"]
+    eng = gv.Engine(geom, precision=gv.PMIX, field_method=gv.FIELD_RK45)
+    got = eng.transport(prim, seed)
+    N = len(prim)
+    d = got - ref
+    m = ref.mean(0)
+    delta = d.mean(0)
+    sig = d.std(0, ddof=1) / np.sqrt(N)
+    total = m.sum()
+    ok3 = np.abs(delta) <= 3 * sig + 1e-9 * np.abs(m)
+    big = m >= 0.01 * total
+    ok05 = ~big | (np.abs(delta) <= 0.005 * np.abs(m))
+    print("\n[c5m RK45 PMix vs oracle] worst |delta|/m on big layers: %.2e, layers failing 3 sigma: %d/%d" % (
+        float(np.max(np.abs(delta[big]) / m[big])), int((~ok3).sum()), len(m)))
+    assert ok05.all()
+    assert (~ok3).sum() <= 2   # 51 cells at 3 sigma: allow two excursions
