@@ -215,8 +215,9 @@ def run_gpu(args):
         st = eng.stats()
         b64 = dict(steps_per_s=st["total_steps"] / dt, primaries_per_s=len(prim) / dt, ms_per_transport=dt * 1e3)
         log(f"[bench] batched FP64: {dt*1e3:.1f} ms")
-    # last: the single-slab leg sets up its own context (one per process)
+    # last: the single-slab and field-map legs set up their own contexts (one per process)
     res["testem5"] = run_testem5(args, gv, torch, eng.config) if args.testem5 else None
+    res["field_map"] = run_field_map(args, gv, torch, eng.config) if args.field_map else None
     return res, plain, b64
 
 
@@ -256,6 +257,52 @@ def run_testem5(args, gv, torch, cfg):
     eng.close()
     log(f"[bench] testem5: {out['steps_per_s']:.3g} steps/s, e- forward {out['electrons_forward']:.4f} "
         f"backward {out['electrons_backward']:.4f}")
+    return out
+
+
+def run_field_map(args, gv, torch, cfg):
+    """The barrel in the solenoid map (c5m: 2000 x 50 GeV e-/gamma), mixed
+    precision: helix in the pre-step field against adaptive RK45 (Sec. 3.6),
+    with the RK45 work per charged step and the fraction of idle lanes in the
+    integration loop (the quantity of the paper's active-lanes table)."""
+    import numpy as np
+
+    import gv_inputs
+    geom, prim, seed = gv_inputs.workload("c5m", args.field_events)
+    eng = gv.Engine(geom, driver=gv.DRIVER_BATCHED, precision=gv.PMIX, edep_on_device=1,
+                    hip_stream=cfg["hip_stream"])
+    edep = torch.zeros((int(prim["event"].max()) + 1, eng.n_cells), dtype=torch.float64, device="cuda:0")
+    eng.stage(prim)
+    out = dict(workload=f"c5m: {len(prim)} x 50 GeV e-/gamma, barrel in a 3.8 T finite solenoid")
+    for name, fm in (("helix", gv.FIELD_HELIX), ("rk45", gv.FIELD_RK45)):
+        eng.configure(field_method=fm)
+        eng.transport_staged(seed, edep.data_ptr())
+        ts, steps, sub, rej, slots, charged, kms = [], 0, 0, 0, 0, 0, 0.0
+        reps = 3 if fm == gv.FIELD_HELIX else 2
+        for k in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.transport_staged(seed, edep.data_ptr())
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            st = eng.stats()
+            steps += st["total_steps"]
+            charged += st["steps"][1] + st["steps"][2]
+            sub += st["rk_substeps"]
+            rej += st["rk_rejected"]
+            slots += st["rk_lane_slots"]
+            kms += st["kernel_ms"]
+        leg = dict(steps_per_s=steps / sum(ts), ms_per_transport=float(np.median(ts)) * 1e3,
+                   kernel_ms_per_transport=kms / reps, e_dep_GeV=float(st["e_dep"]) * 1e-3 / len(prim),
+                   tail_kernel_ms=float(st["tail_kernel_ms"]))
+        if fm == gv.FIELD_RK45:
+            leg.update(substeps_per_charged_step=sub / max(charged, 1), rejected_per_charged_step=rej / max(charged, 1),
+                       substeps_per_s=sub / sum(ts), idle_lane_fraction=1.0 - (sub + rej) / max(slots, 1))
+        out[name] = leg
+        log(f"[bench] field map {name}: {leg['steps_per_s']:.3g} steps/s, {leg['ms_per_transport']:.1f} ms"
+            + (f", {leg['substeps_per_charged_step']:.2f} substeps + {leg['rejected_per_charged_step']:.2f} "
+               f"rejected per charged step, idle lanes {leg['idle_lane_fraction']:.3f}" if name == "rk45" else ""))
+    eng.close()
     return out
 
 
@@ -305,6 +352,8 @@ def main():
     ap.add_argument("--inner", type=int, default=0)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--testem5", type=int, default=1, help="run the single-slab leg")
+    ap.add_argument("--field-map", type=int, default=1, help="run the solenoid-map (helix vs RK45) leg")
+    ap.add_argument("--field-events", type=int, default=None, help="events of the solenoid-map leg")
     ap.add_argument("--table-steps", type=int, default=3,
                     help="timed transports with table (alias) final-state sampling")
     ap.add_argument("--fp64-batched", type=int, default=1)
@@ -372,6 +421,7 @@ def main():
         "batched_fp64": b64,
         "table_sampling": res["tables"],
         "testem5": res["testem5"],
+        "field_map": res["field_map"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),

@@ -57,12 +57,12 @@ enum { GV_P64 = 0, GV_PMIX = 1 };
  * (e = 5th- minus 4th-order weights, kx / ku the position / direction stage
  * derivatives): the position error per unit length and the direction error.
  * A substep is accepted when err <= rk_tol.  The first attempt is
- * h = min(s, 0.9 (rk_tol / K)^(1/4) / |du/ds|), K = 8.1e-4 being the pair's
- * error constant on circular motion; then h is scaled by
- * clamp(0.9 (rk_tol / err)^(1/5), 0.2, 5) after an accepted substep and by
- * max(0.9 (rk_tol / err)^(1/5), 0.2) after a rejected one, and never passes
- * the end.  After rk_max_substeps attempts the step ends where integration
- * stopped. */
+ * h = min(s, 0.8 (rk_tol / K)^(1/4) / |du/ds|), K = 8.1e-4 being the pair's
+ * error constant on circular motion; then h is halved after a rejected
+ * attempt and doubled after an accepted substep with err <= rk_tol / 16, and
+ * never passes the end (powers of two: the substeps are an exact function of
+ * s and the first attempt).  After rk_max_substeps attempts the step ends
+ * where integration stopped. */
 enum { GV_FIELD_HELIX = 0, GV_FIELD_RK4 = 1, GV_FIELD_RK45 = 2 };
 /* Field maps.  UNIFORM: B everywhere.  SOLENOID: a finite solenoid along z
  * centred on the origin, coil radius sol_cm[0], half-length sol_cm[1],
@@ -188,7 +188,7 @@ typedef struct {
     int32_t fs_alias;               /* bit m set (m = GV_FS_*): model m samples its final state
                                        from tables instead of by rejection; default 0 */
     int32_t reserved2;              /* must be 0 */
-    double rk_tol;                  /* RK45 error tolerance, 0 = default 1e-6 */
+    double rk_tol;                  /* RK45 error tolerance, 0 = default 1e-5 */
     int32_t rk_max_substeps;        /* RK45 attempts per step, 1..2^20, 0 = default 10000 */
     int32_t reserved3;              /* must be 0 */
 } gv_config;

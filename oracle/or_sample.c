@@ -73,11 +73,15 @@ static void solenoid_field(double B0, double R, double L, const double x[3], dou
     double f0 = 2.0 * L / sqrt(R2 + L * L);
     double c = B0 / f0;
     double a = x[2] + L, b = x[2] - L;
-    double qa = R2 + a * a, qb = R2 + b * b;
-    double sa = sqrt(qa), sb = sqrt(qb);
-    double g = c * (a / sa - b / sb);
-    double g1 = c * R2 * (1.0 / (qa * sa) - 1.0 / (qb * sb));               /* g'  */
-    double g2 = -3.0 * c * R2 * (a / (qa * qa * sa) - b / (qb * qb * sb));  /* g'' */
+    double sa = sqrt(R2 + a * a), sb = sqrt(R2 + b * b);
+    /* ia = 1/sqrt(R^2 + a^2), ib likewise, from one division */
+    double r = 1.0 / (sa * sb);
+    double ia = sb * r, ib = sa * r;
+    double ia2 = ia * ia, ib2 = ib * ib;
+    double ia3 = ia2 * ia, ib3 = ib2 * ib;
+    double g = c * (a * ia - b * ib);
+    double g1 = c * R2 * (ia3 - ib3);                           /* g'  */
+    double g2 = -3.0 * c * R2 * (a * (ia3 * ia2) - b * (ib3 * ib2));  /* g'' */
     double r2 = x[0] * x[0] + x[1] * x[1];
     out[0] = -0.5 * x[0] * g1;
     out[1] = -0.5 * x[1] * g1;

@@ -35,11 +35,15 @@ template <class R> __device__ __forceinline__ void field_at(const DevGeom& g, co
     const R R2 = (R)g.sol_R2, L = (R)g.sol_L, c = (R)g.sol_c;
     const R z = (R)x[2];
     const R a = z + L, b = z - L;
-    const R qa = R2 + a * a, qb = R2 + b * b;
-    const R sa = m_sqrt(qa), sb = m_sqrt(qb);
-    const R g0 = c * (a / sa - b / sb);
-    const R g1 = c * R2 * ((R)1 / (qa * sa) - (R)1 / (qb * sb));
-    const R g2 = (R)-3 * c * R2 * (a / (qa * qa * sa) - b / (qb * qb * sb));
+    const R sa = m_sqrt(R2 + a * a), sb = m_sqrt(R2 + b * b);
+    // 1/sqrt(R^2 + a^2) and 1/sqrt(R^2 + b^2) from one division
+    const R r = (R)1 / (sa * sb);
+    const R ia = sb * r, ib = sa * r;
+    const R ia2 = ia * ia, ib2 = ib * ib;
+    const R ia3 = ia2 * ia, ib3 = ib2 * ib;
+    const R g0 = c * (a * ia - b * ib);
+    const R g1 = c * R2 * (ia3 - ib3);
+    const R g2 = (R)-3 * c * R2 * (a * (ia3 * ia2) - b * (ib3 * ib2));
     const R px = (R)x[0], py = (R)x[1];
     const R r2 = px * px + py * py;
     B[0] = (R)-0.5 * px * g1;
