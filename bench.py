@@ -215,6 +215,27 @@ def run_gpu(args):
         st = eng.stats()
         b64 = dict(steps_per_s=st["total_steps"] / dt, primaries_per_s=len(prim) / dt, ms_per_transport=dt * 1e3)
         log(f"[bench] batched FP64: {dt*1e3:.1f} ms")
+    # one GPU's share of an 8-way event split of the same batch, in one
+    # transport: the population, and so the occupancy, is 8x smaller
+    share = None
+    if args.share_events > 0 and args.share_events < n_events:
+        eng.configure(driver=gv.DRIVER_BATCHED, precision=gv.PMIX)
+        sub = prim[prim["event"] < args.share_events]
+        eng.stage(sub)
+        eng.transport_staged(seed, edep.data_ptr())
+        ts, ssteps = [], 0
+        for k in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.transport_staged(seed + k, edep.data_ptr())
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            ssteps += eng.stats()["total_steps"]
+        share = dict(events=int(args.share_events), steps_per_s=ssteps / sum(ts),
+                     median_ms_per_transport=float(np.median(ts)) * 1e3)
+        log(f"[bench] one GPU's share ({args.share_events} events): {share['steps_per_s']:.3g} steps/s")
+        eng.stage(prim)
+    res["share"] = share
     # last: the single-slab and field-map legs set up their own contexts (one per process)
     res["testem5"] = run_testem5(args, gv, torch, eng.config) if args.testem5 else None
     res["field_map"] = run_field_map(args, gv, torch, eng.config) if args.field_map else None
@@ -353,6 +374,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--testem5", type=int, default=1, help="run the single-slab leg")
     ap.add_argument("--field-map", type=int, default=1, help="run the solenoid-map (helix vs RK45) leg")
+    ap.add_argument("--share-events", type=int, default=1250,
+                    help="events of the one-GPU-share leg (an 8-way split of the batch); 0 = skip")
     ap.add_argument("--field-events", type=int, default=None, help="events of the solenoid-map leg")
     ap.add_argument("--table-steps", type=int, default=3,
                     help="timed transports with table (alias) final-state sampling")
@@ -422,6 +445,7 @@ def main():
         "table_sampling": res["tables"],
         "testem5": res["testem5"],
         "field_map": res["field_map"],
+        "one_gpu_share": res["share"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),

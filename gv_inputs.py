@@ -79,7 +79,7 @@ TABLE_SPEC = dict(e_min=1.0e-3, bins_per_decade=100, n_nodes=801,
 # Transport constants that are run parameters rather than physics.
 RUN_SPEC = dict(chord_tol=1.0e-3, push=1.0e-7, rk_frac=0.05,
                 max_steps=1 << 20, field_method=0, fs_alias=0,
-                rk_tol=1.0e-5, rk_max_sub=10000)
+                rk_tol=1.0e-5, rk_max_sub=16)
 
 
 def material_list(names):

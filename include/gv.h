@@ -189,7 +189,7 @@ typedef struct {
                                        from tables instead of by rejection; default 0 */
     int32_t reserved2;              /* must be 0 */
     double rk_tol;                  /* RK45 error tolerance, 0 = default 1e-5 */
-    int32_t rk_max_substeps;        /* RK45 attempts per step, 1..2^20, 0 = default 10000 */
+    int32_t rk_max_substeps;        /* RK45 attempts per step, 1..2^20, 0 = default 16 */
     int32_t reserved3;              /* must be 0 */
 } gv_config;
 

@@ -465,7 +465,7 @@ int apply_run_params()
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
     L.phys.rk_tol = L.cfg.rk_tol > 0.0 ? L.cfg.rk_tol : 1.0e-5;
-    L.phys.rk_max_sub = L.cfg.rk_max_substeps > 0 ? L.cfg.rk_max_substeps : 10000;
+    L.phys.rk_max_sub = L.cfg.rk_max_substeps > 0 ? L.cfg.rk_max_substeps : 16;
     L.phys.max_steps = L.cfg.max_steps_per_track;
     L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_phys), &L.phys, sizeof(DevPhys), 0, hipMemcpyHostToDevice, stream()));
@@ -1136,7 +1136,7 @@ int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom, co
     L.phys.push = L.cfg.push_cm;
     L.phys.rk_frac = L.cfg.rk_frac;
     L.phys.rk_tol = 1.0e-5;
-    L.phys.rk_max_sub = 10000;
+    L.phys.rk_max_sub = 16;
     L.phys.max_steps = L.cfg.max_steps_per_track;
     L.phys.fs_alias = L.cfg.fs_alias;
     HIPCHK(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_geom), &L.geom, sizeof(DevGeom), 0, hipMemcpyHostToDevice, stream()));

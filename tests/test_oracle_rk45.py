@@ -284,11 +284,12 @@ def test_transport_with_rk45_in_the_map(oracle_mod):
 
 
 def test_rk45_uniform_field_single_steps_match_helix(oracle_mod):
+    # no attempt cap here: every step is integrated over its full length
     geom = gv_inputs.slab_calorimeter(4, (0.0, 4.0, 0.0))
     st = gv_inputs.random_states(400, 31, geom)
     a = oracle_mod.Oracle(geom).single_step(st, 5)
     b = oracle_mod.Oracle(geom, run_spec={"field_method": oracle_mod.FIELD_RK45,
-                                          "rk_tol": 1e-9}).single_step(st, 5)
+                                          "rk_tol": 1e-9, "rk_max_sub": 100000}).single_step(st, 5)
     charged = st["type"] != 0
     assert charged.sum() > 100
     # same step lengths and limiters; positions within the tolerance per length
