@@ -50,17 +50,19 @@ def kernel_source_hash():
 def measured_traffic(steps_per_launch, workload, knobs):
     """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE counters
     (per step, calibrated against a plain copy), or None when the kernel
-    sources changed since they were taken, or the workload or the knobs
-    (basket, occupancy, inner steps) differ."""
+    sources changed since they were taken, the workload differs, or no
+    recorded entry has these knobs (basket, occupancy, inner steps)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if (t.get("source_sha1") != kernel_source_hash() or t.get("workload") != workload
-            or t.get("knobs") != list(knobs)):
+    if t.get("source_sha1") != kernel_source_hash() or t.get("workload") != workload:
         return None
-    return t["bytes_per_step"] * steps_per_launch
+    for e in t.get("entries", []):
+        if e.get("knobs") == list(knobs):
+            return e["bytes_per_step"] * steps_per_launch
+    return None
 
 
 def log(msg):

@@ -171,7 +171,7 @@ typedef struct {
                                        of >= 4096 primaries (trial transports of a sample of
                                        the batch, choice cached per precision, order and batch
                                        size class), otherwise they take the defaults
-                                       256 / 4 / 4 */
+                                       256 / 3 / 4 */
     int32_t graph_steps;            /* step launches per captured graph, 0 = default */
     int32_t field_method;           /* GV_FIELD_HELIX, GV_FIELD_RK4 or GV_FIELD_RK45 */
     int32_t edep_on_device;         /* edep_out of gv_transport is a device pointer */

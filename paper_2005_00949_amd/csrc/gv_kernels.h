@@ -804,9 +804,12 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
 }
 
 // INTEG: field integrators compiled in (field_method RK4 / RK45); the helix
-// variant leaves them out and keeps its register budget.
+// variant leaves them out and keeps its register budget.  The mixed-precision
+// helix variant is held to three wavefronts per SIMD (168 VGPRs): the step
+// chain is latency-bound, and a third resident wavefront hides more of it.
 template <class P, int BLOCK, bool STABLE, bool INTEG>
-__global__ void __launch_bounds__(BLOCK) k_step_batched(BatchArgs<P> A)
+__global__ void __launch_bounds__(BLOCK, (!INTEG && sizeof(typename P::R) == sizeof(float)) ? 3 : 1)
+k_step_batched(BatchArgs<P> A)
 {
     __shared__ ScanShared<BLOCK> sh;
     __shared__ unsigned cnt_lds[kNCount];

@@ -483,7 +483,7 @@ struct Tuning {
 };
 
 // default knob values, used for small batches and as the autotuner's start
-constexpr int kDefBasket = 256, kDefOccupancy = 4, kDefInner = 4;
+constexpr int kDefBasket = 256, kDefOccupancy = 3, kDefInner = 4;
 // batches below this many primaries are not autotuned
 constexpr int64_t kTuneMinPrimaries = 4096;
 
@@ -923,13 +923,13 @@ template <class P> int tuned_choice(int64_t n_events, uint64_t seed, std::array<
     double best_rate = 0.0;
     int rc = trial(best, best_rate);
     if (rc) return rc;
-    static const int kCand[3][4] = {{64, 128, 256, 512}, {1, 2, 4, 8}, {1, 2, 4, 8}};
+    static const int kCand[3][6] = {{64, 128, 256, 512, 0, 0}, {1, 2, 3, 4, 6, 8}, {1, 2, 4, 8, 0, 0}};
     const int fixed[3] = {L.cfg.basket, L.cfg.occupancy, L.cfg.inner_steps};
     for (int knob : {2, 0, 1}) {
         if (fixed[knob]) continue;
         const std::array<int, 3> base = best;
         for (int v : kCand[knob]) {
-            if (v == base[knob]) continue;
+            if (v == 0 || v == base[knob]) continue;
             std::array<int, 3> c = base;
             c[knob] = v;
             double r = 0.0;

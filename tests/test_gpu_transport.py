@@ -230,7 +230,7 @@ def test_autotuner_choice_is_cached_and_exact(gv):
     e1 = eng.transport(prim, seed)
     st1 = eng.stats()
     assert st1["tuned"] == 1 and st1["autotune_ms"] > 0
-    assert st1["basket"] in (64, 128, 256, 512) and st1["occupancy"] in (1, 2, 4, 8)
+    assert st1["basket"] in (64, 128, 256, 512) and st1["occupancy"] in (1, 2, 3, 4, 6, 8)
     assert st1["inner_steps"] in (1, 2, 4, 8)
     e2 = eng.transport(prim, seed)
     st2 = eng.stats()
