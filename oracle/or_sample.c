@@ -201,7 +201,8 @@ static void dp_deriv(const or_field* f, double kq, const double y[6], double k[6
  *   the end of the interval.  Powers of two keep every substep length an
  *   exact function of s and theta, so any two IEEE implementations take the
  *   same substeps.  Stops after max_sub attempts.  Sums over stages run in
- *   stage order. */
+ *   stage order as fused multiply-adds (fma), as does the stage point
+ *   y + h sum. */
 #define RK45_K 8.1e-4
 int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, double tol,
                      int32_t max_sub, double pos[3], double dir[3], double* s_done, int32_t* n_rej)
@@ -230,8 +231,8 @@ int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, dou
         for (int i = 1; i < 7; ++i) {
             for (int c = 0; c < 6; ++c) {
                 double sum = DP_A[i][0] * k[0][c];
-                for (int j = 1; j < i; ++j) sum += DP_A[i][j] * k[j][c];
-                yi[c] = y[c] + h * sum;
+                for (int j = 1; j < i; ++j) sum = fma(DP_A[i][j], k[j][c], sum);
+                yi[c] = fma(h, sum, y[c]);
             }
             dp_deriv(f, kq, yi, k[i]);
         }
@@ -239,7 +240,7 @@ int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, dou
         double err = 0.0;
         for (int c = 0; c < 6; ++c) {
             double e = (DP_B[0] - DP_BH[0]) * k[0][c];
-            for (int j = 1; j < 7; ++j) e += (DP_B[j] - DP_BH[j]) * k[j][c];
+            for (int j = 1; j < 7; ++j) e = fma(DP_B[j] - DP_BH[j], k[j][c], e);
             if (c >= 3) e = h * e;
             if (fabs(e) > err) err = fabs(e);
         }

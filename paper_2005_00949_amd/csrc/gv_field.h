@@ -144,8 +144,9 @@ constexpr double kDpK = 8.1e-4;
 // Next h: halved after a rejected attempt, doubled after an accepted substep
 // with error <= tol/16, cut to end exactly at s; powers of two keep every
 // substep length an exact function of s and theta.  After max_sub attempts
-// the integration stops.  Stage sums run in stage order (zero coefficients
-// skipped).  Returns the length integrated (s unless attempts ran out).
+// the integration stops.  Stage sums run in stage order as fused
+// multiply-adds (zero coefficients skipped), as does the stage point
+// y + h sum.  Returns the length integrated (s unless attempts ran out).
 //
 // The loop runs while any lane of the wavefront still integrates, each lane
 // working only while it has work: every lane then knows how many iterations
@@ -193,12 +194,12 @@ __device__ inline double rk45_move(const DevGeom& g, int type, double T, double 
 #pragma unroll
                 for (int j = 1; j < i; ++j) {
                     if (kDpA[i][j] != 0.0) {
-                        sx += kDpA[i][j] * kx[j][a];
-                        su += kDpA[i][j] * ku[j][a];
+                        sx = fma(kDpA[i][j], kx[j][a], sx);
+                        su = fma(kDpA[i][j], ku[j][a], su);
                     }
                 }
-                xs[a] = pos[a] + h * sx;
-                us[a] = u[a] + h * su;
+                xs[a] = fma(h, sx, pos[a]);
+                us[a] = fma(h, su, u[a]);
             }
             double B[3];
             field_at<double>(g, xs, B);
@@ -212,14 +213,14 @@ __device__ inline double rk45_move(const DevGeom& g, int type, double T, double 
         for (int a = 0; a < 3; ++a) {
             double ex = kDpE[0] * kx[0][a];
 #pragma unroll
-            for (int j = 2; j < 7; ++j) ex += kDpE[j] * kx[j][a];
+            for (int j = 2; j < 7; ++j) ex = fma(kDpE[j], kx[j][a], ex);
             if (fabs(ex) > err) err = fabs(ex);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             double eu = kDpE[0] * ku[0][a];
 #pragma unroll
-            for (int j = 2; j < 7; ++j) eu += kDpE[j] * ku[j][a];
+            for (int j = 2; j < 7; ++j) eu = fma(kDpE[j], ku[j][a], eu);
             eu = h * eu;
             if (fabs(eu) > err) err = fabs(eu);
         }
