@@ -115,6 +115,7 @@ def run_gpu(args):
             f"inner {st['inner_steps']}")
     torch.cuda.synchronize()
     steps = prims = 0
+    lane_slots = 0
     kernel_ms = 0.0
     launches = 0
     alg_bytes = 0.0
@@ -125,6 +126,7 @@ def run_gpu(args):
         eng.transport_staged(seed + k, edep.data_ptr())
         st = eng.stats()
         steps += st["total_steps"]
+        lane_slots += st["lane_slots"]
         prims += len(prim)
         kernel_ms += st["kernel_ms"]
         launches += st["kernel_launches"]
@@ -140,7 +142,7 @@ def run_gpu(args):
     elapsed = time.perf_counter() - t0
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
                alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
-               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms)
+               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots)
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
@@ -438,6 +440,9 @@ def main():
         "ms_per_transport": [round(x, 2) for x in res["per_ms"]],
         "tail_ms_per_transport": [round(x, 2) for x in res["tail_ms"]],
         "autotune_ms": res["autotune_ms"],
+        # share of the stepping loop's lane slots that took a step (steps over
+        # 64 x loop iterations of every wavefront, timed transports)
+        "lane_use": res["steps"] / res["lane_slots"] if res["lane_slots"] else None,
         "pcie_inclusive": {"ms_per_transport": res["pcie_inclusive_ms"],
                            "steps_per_s": res["pcie_inclusive_steps_per_s"]},
         "track_steps_per_transport": res["steps"] / args.steps,

@@ -231,6 +231,10 @@ typedef struct {
                                        integrate together, (lanes) x (most attempts among
                                        them); 1 - (substeps + rejected) / lane_slots is the
                                        fraction of idle lanes in the integration loop */
+    int64_t lane_slots;             /* batched driver: 64 x (step-loop iterations) summed over the
+                                       wavefronts of every basket, a wavefront running as many
+                                       iterations as its busiest lane; total steps / lane_slots is
+                                       the lane use of the stepping loop (0 for the plain driver) */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

@@ -84,7 +84,7 @@ __device__ __forceinline__ void store_child(const Soa<P>& q, size_t i, const Tra
 
 // global counters (gv_stats)
 enum : int { kCSteps = 0, kCTracks = 3, kCProc = 6, kCEscaped = 14, kCKilled = 15, kCRej = 16, kCLoads = 17,
-             kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kNCount = 22 };
+             kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kCLaneSlots = 22, kNCount = 23 };
 
 // per-lane sums of the adaptive-integration tallies over one launch
 struct RkSum {
@@ -716,7 +716,8 @@ template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, class R = typenam
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
-                                              uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks)
+                                              uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks,
+                                              unsigned long long* lane_slots_lds)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -726,16 +727,18 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
     o.nchild = 0;
     o.ch[0].type = -1;
     o.ch[1].type = -1;
+    int iters = 0;
     if (active) {
         load_track(A.in[TY], slot, TY, t);
         t.type = TY;
         loads += 1;
         DepAcc acc{0.0, 0ull};
         int acc_vol = t.vol;
-        for (int k = 0; k < inner; ++k) {
+        for (; iters < inner;) {
             const uint32_t ns = t.nstep;
             step_track<P, INTEG>(c, t, o);
             steps_here += o.did_step;
+            iters += 1;
             if (TY != kGamma) {
                 rks.acc += (uint32_t)o.rk.acc;
                 rks.rej += (uint32_t)o.rk.rej;
@@ -754,6 +757,13 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
             if (o.status != kAlive || o.nchild > 0) break;
         }
         dep_add(dc, A.S, t.ev, acc_vol, acc);
+    }
+    {
+        // lane use: the wavefront ran as many loop iterations as its busiest lane
+        int m = iters;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(lane_slots_lds, 64ull * (unsigned)m);
     }
     dep_flush<BLOCK>(dc, A.S);
     const int alive = (active && o.status == kAlive) ? 1 : 0;
@@ -813,10 +823,10 @@ k_step_batched(BatchArgs<P> A)
 {
     __shared__ ScanShared<BLOCK> sh;
     __shared__ unsigned cnt_lds[kNCount];
-    __shared__ unsigned long long rk_lds[3];
+    __shared__ unsigned long long rk_lds[4];
     __shared__ DepCache dc;
     for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
-    if (threadIdx.x < 3) rk_lds[threadIdx.x] = 0ull;
+    if (threadIdx.x < 4) rk_lds[threadIdx.x] = 0ull;
     dep_clear<BLOCK>(dc);
 
     const int pin = A.parity;
@@ -854,13 +864,13 @@ k_step_batched(BatchArgs<P> A)
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
                 process_chunk<P, kGamma, BLOCK, STABLE, INTEG>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
-                                                loads, stores, n_chunks, rks);
+                                                loads, stores, n_chunks, rks, &rk_lds[3]);
             else if (chunk < c0 + c1)
                 process_chunk<P, kElectron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
-                                                   steps_e, loads, stores, n_chunks, rks);
+                                                   steps_e, loads, stores, n_chunks, rks, &rk_lds[3]);
             else
                 process_chunk<P, kPositron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
-                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks);
+                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks, &rk_lds[3]);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);
@@ -876,7 +886,7 @@ k_step_batched(BatchArgs<P> A)
     __syncthreads();
     for (int i = threadIdx.x; i < kNCount; i += BLOCK)
         if (cnt_lds[i]) atomicAdd(&A.S.counters[i], (unsigned long long)cnt_lds[i]);
-    if (threadIdx.x < 3 && rk_lds[threadIdx.x]) atomicAdd(&A.S.counters[kCRkSub + threadIdx.x], rk_lds[threadIdx.x]);
+    if (threadIdx.x < 4 && rk_lds[threadIdx.x]) atomicAdd(&A.S.counters[kCRkSub + threadIdx.x], rk_lds[threadIdx.x]);
     finish_launch(A.ctrl, pin, participants);
 }
 

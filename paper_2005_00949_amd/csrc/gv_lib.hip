@@ -1285,6 +1285,7 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     L.stats.rk_substeps = (int64_t)cnt[kCRkSub];
     L.stats.rk_rejected = (int64_t)cnt[kCRkRej];
     L.stats.rk_lane_slots = (int64_t)cnt[kCRkSlots];
+    L.stats.lane_slots = (int64_t)cnt[kCLaneSlots];
     L.stats.trace_records = (int64_t)std::min<unsigned long long>(tn, (unsigned long long)L.cfg.trace_cap);
     L.stats.e_in = L.e_in;
     double ed = 0.0, es = 0.0, ek = 0.0, np_ = 0.0, na = 0.0;

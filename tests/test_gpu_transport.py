@@ -124,6 +124,23 @@ def test_ledger_closure(gv, name, n, mode):
     assert st["killed"] == 0
 
 
+@pytest.mark.parametrize("driver", ["plain", "batched"])
+def test_lane_use_counter(gv, driver):
+    """lane_slots counts 64 lanes per step-loop iteration of every wavefront:
+    never fewer than the steps taken, and 0 for the plain driver."""
+    geom, prim, seed = gv_inputs.workload("c3", 30)
+    eng = gv.Engine(geom, precision=gv.P64, driver=gv.DRIVER_PLAIN if driver == "plain" else gv.DRIVER_BATCHED,
+                    basket=128, inner_steps=4)
+    eng.transport(prim, seed)
+    st = eng.stats()
+    if driver == "plain":
+        assert st["lane_slots"] == 0
+    else:
+        use = st["total_steps"] / st["lane_slots"]
+        print(f"\n[c3 batched] lane use {use:.3f}")
+        assert 0.05 < use <= 1.0
+
+
 def test_determinism_across_knobs(gv):
     geom, prim, seed = gv_inputs.workload("c3", 20)
     ref = None
