@@ -166,3 +166,23 @@ def test_rk45_paired_layer_deposits_mixed_vs_oracle(gv, oracle_mod):
         float(np.max(np.abs(delta[big]) / m[big])), int((~ok3).sum()), len(m)))
     assert ok05.all()
     assert (~ok3).sum() <= 2   # 51 cells at 3 sigma: allow two excursions
+
+
+def test_rk45_fixed_point_scores_bit_identical(gv):
+    """RK45 decisions depend only on a lane's own track (the wavefront loop
+    only counts iterations), so fixed-point scores with RK45 are bit-identical
+    across basket, occupancy, inner steps, queue order and (FP64) driver."""
+    geom, prim, seed = gv_inputs.workload("c5m", 6)
+    prim = prim.copy()
+    prim["ekin"] = 3000.0
+    runs = []
+    for cfg in [dict(driver=gv.DRIVER_PLAIN),
+                dict(basket=256, occupancy=3, inner_steps=4, queue_order=gv.ORDER_ARRIVAL),
+                dict(basket=64, occupancy=1, inner_steps=1, queue_order=gv.ORDER_STABLE),
+                dict(basket=512, occupancy=6, inner_steps=8, queue_order=gv.ORDER_ARRIVAL)]:
+        eng = gv.Engine(geom, precision=gv.P64, field_method=gv.FIELD_RK45, deposit_mode=gv.DEPOSIT_FIXED, **cfg)
+        e = eng.transport(prim, seed)
+        runs.append((e, eng.ledger(), eng.stats()["rk_substeps"]))
+        eng.close()
+    for e, L, sub in runs[1:]:
+        assert np.array_equal(e, runs[0][0]) and np.array_equal(L, runs[0][1]) and sub == runs[0][2]
