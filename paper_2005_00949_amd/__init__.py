@@ -201,9 +201,14 @@ class Engine:
         unknown = set(kw) - set(self.config)
         if unknown:
             raise TypeError(f"unknown options {sorted(unknown)}")
+        old = dict(self.config)
         self.config.update(kw)
         c = Config(**{k: v for k, v in self.config.items()})
-        _check(self.lib.gv_configure(C.byref(c)))
+        try:
+            _check(self.lib.gv_configure(C.byref(c)))
+        except GvError:
+            self.config = old          # the library keeps its previous configuration too
+            raise
 
     def transport(self, primaries, seed, edep_out=None):
         """primaries: gv_inputs.PRIMARY_DTYPE array.  Returns edep [events, cells]
