@@ -243,6 +243,7 @@ def run_gpu(args):
     # last: the single-slab and field-map legs set up their own contexts (one per process)
     res["testem5"] = run_testem5(args, gv, torch, eng.config) if args.testem5 else None
     res["field_map"] = run_field_map(args, gv, torch, eng.config) if args.field_map else None
+    res["barrel"] = run_barrel_precision(args, gv, torch, eng.config) if args.barrel else None
     return res, plain, b64
 
 
@@ -282,6 +283,41 @@ def run_testem5(args, gv, torch, cfg):
     eng.close()
     log(f"[bench] testem5: {out['steps_per_s']:.3g} steps/s, e- forward {out['electrons_forward']:.4f} "
         f"backward {out['electrons_backward']:.4f}")
+    return out
+
+
+def run_barrel_precision(args, gv, torch, cfg):
+    """The barrel in its 3.8 T field (c5: 2000 x 50 GeV e-/gamma): mixed
+    precision against all-FP64, both batched on the GPU, on the same seed:
+    throughput of each and the paired per-cell deposit comparison."""
+    import numpy as np
+
+    import gv_inputs
+    geom, prim, seed = gv_inputs.workload("c5")
+    eng = gv.Engine(geom, driver=gv.DRIVER_BATCHED, precision=gv.PMIX, edep_on_device=1,
+                    hip_stream=cfg["hip_stream"])
+    n_ev = int(prim["event"].max()) + 1
+    edep = torch.zeros((n_ev, eng.n_cells), dtype=torch.float64, device="cuda:0")
+    eng.stage(prim)
+    out = dict(workload=f"c5: {len(prim)} x 50 GeV e-/gamma, barrel, 3.8 T along z")
+    res = {}
+    for name, prec in (("pmix", gv.PMIX), ("p64", gv.P64)):
+        eng.configure(precision=prec)
+        eng.transport_staged(seed, edep.data_ptr())
+        ts, steps = [], 0
+        for k in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.transport_staged(seed, edep.data_ptr())
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            steps += eng.stats()["total_steps"]
+        res[name] = edep.cpu().numpy()
+        out[name] = dict(steps_per_s=steps / sum(ts), ms_per_transport=float(np.median(ts)) * 1e3)
+    out["pmix_vs_p64"] = paired_layers(res["pmix"], res["p64"])
+    eng.close()
+    log(f"[bench] barrel c5: mixed {out['pmix']['steps_per_s']:.3g} steps/s, FP64 {out['p64']['steps_per_s']:.3g} "
+        f"steps/s, per-cell worst {out['pmix_vs_p64']['worst_rel_big_layers']:.2e}")
     return out
 
 
@@ -381,6 +417,7 @@ def main():
     ap.add_argument("--share-events", type=int, default=1250,
                     help="events of the one-GPU-share leg (an 8-way split of the batch); 0 = skip")
     ap.add_argument("--field-events", type=int, default=None, help="events of the solenoid-map leg")
+    ap.add_argument("--barrel", type=int, default=1, help="run the barrel mixed-vs-FP64 leg")
     ap.add_argument("--table-steps", type=int, default=3,
                     help="timed transports with table (alias) final-state sampling")
     ap.add_argument("--fp64-batched", type=int, default=1)
@@ -452,6 +489,7 @@ def main():
         "table_sampling": res["tables"],
         "testem5": res["testem5"],
         "field_map": res["field_map"],
+        "barrel_precision": res["barrel"],
         "one_gpu_share": res["share"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
