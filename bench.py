@@ -381,10 +381,30 @@ def run_cpu_baseline(args):
     dt = time.perf_counter() - t
     c = r["counters"]
     steps = c["steps_gamma"] + c["steps_electron"] + c["steps_positron"]
+    # one thread on a tenth of the sample, for the per-core rate
+    small = prim[prim["event"] < max(1, args.cpu_events // 10)]
+    t = time.perf_counter()
+    r1 = o.transport(small, seed, n_threads=1)
+    dt1 = time.perf_counter() - t
+    c1 = r1["counters"]
+    steps1 = c1["steps_gamma"] + c1["steps_electron"] + c1["steps_positron"]
     return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
                 sample=f"first {args.cpu_events} events of the same batch ({len(sample)} primaries, "
                        f"{steps} steps, {dt:.1f} s, FP64 history-based, {threads} threads)",
-                primaries_per_s=len(sample) / dt)
+                primaries_per_s=len(sample) / dt, cpu_model=cpu_model(),
+                single_thread_steps_per_s=steps1 / dt1,
+                single_thread_sample=f"first {len(small)} events, {steps1} steps, {dt1:.1f} s")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def copy_probe(nbytes, reps):
