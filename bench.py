@@ -106,10 +106,12 @@ def run_gpu(args):
     log(f"[bench] workload {args.workload}: {len(prim)} primaries, {n_events} events, "
         f"{eng.n_cells} cells; warmup {args.warmup}, steps {args.steps}")
     tune_ms = 0.0
+    warm_ms = []
     for w in range(args.warmup):
         eng.transport_staged(seed, edep.data_ptr())
         st = eng.stats()
         tune_ms += st["autotune_ms"]
+        warm_ms.append(round(st["transport_ms"], 2))
         log(f"[bench] warmup {w}: {st['transport_ms']:.1f} ms ({st['autotune_ms']:.1f} ms autotuning), "
             f"{st['total_steps']} steps, basket {st['basket']} occupancy {st['occupancy']} "
             f"inner {st['inner_steps']}")
@@ -142,7 +144,7 @@ def run_gpu(args):
     elapsed = time.perf_counter() - t0
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
                alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
-               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots)
+               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots, warm_ms=warm_ms)
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
@@ -497,6 +499,10 @@ def main():
         "ms_per_transport": [round(x, 2) for x in res["per_ms"]],
         "tail_ms_per_transport": [round(x, 2) for x in res["tail_ms"]],
         "autotune_ms": res["autotune_ms"],
+        # set-up outside the timed steps: gv_init (tables built on the device)
+        # and the warm-up transports (autotuning and graph capture included)
+        "init_ms": st0["init_ms"],
+        "warmup_ms": res["warm_ms"],
         # share of the stepping loop's lane slots that took a step (steps over
         # 64 x loop iterations of every wavefront, timed transports)
         "lane_use": res["steps"] / res["lane_slots"] if res["lane_slots"] else None,
