@@ -73,20 +73,32 @@ __device__ __forceinline__ int stack_of(const DevGeom& g, double c)
     return lo + 1;
 }
 
-__device__ inline int locate(const DevGeom& g, const double p[3])
+// stack_of with a guess: a point that has moved stays in its volume or enters
+// a neighbour, so the guessed volumes are tried before the binary search (the
+// answer is the same: bounds[v-1] <= c < bounds[v] holds for one v only, and
+// the two ends of the stack fall through to stack_of's own rules)
+__device__ __forceinline__ int stack_of_near(const DevGeom& g, double c, int v0, int v1)
+{
+    if (v0 >= 1 && v0 <= g.n_vol && g.bounds[v0 - 1] <= c && c < g.bounds[v0]) return v0;
+    if (v1 >= 1 && v1 <= g.n_vol && g.bounds[v1 - 1] <= c && c < g.bounds[v1]) return v1;
+    return stack_of(g, c);
+}
+
+// volume containing p; v0, v1: likely stack volumes (0 or -1: no guess)
+__device__ inline int locate(const DevGeom& g, const double p[3], int v0 = 0, int v1 = 0)
 {
 #pragma clang fp contract(off)
     if (g.axis == 0) {
-        if (fabs(p[0]) <= g.env[0] && fabs(p[1]) <= g.env[1] && p[2] >= g.bounds[0] && p[2] <= g.bounds[g.n_vol])
-            return stack_of(g, p[2]);
-        if (fabs(p[0]) <= g.world[0] && fabs(p[1]) <= g.world[1] && p[2] >= g.world[2] && p[2] <= g.world[3])
-            return 0;
-        return kOutside;
+        const bool in_env = (fabs(p[0]) <= g.env[0]) & (fabs(p[1]) <= g.env[1]) & (p[2] >= g.bounds[0]) &
+                            (p[2] <= g.bounds[g.n_vol]);
+        if (in_env) return stack_of_near(g, p[2], v0, v1);
+        const bool in_world = (fabs(p[0]) <= g.world[0]) & (fabs(p[1]) <= g.world[1]) & (p[2] >= g.world[2]) &
+                              (p[2] <= g.world[3]);
+        return in_world ? 0 : kOutside;
     }
     const double r = sqrt(p[0] * p[0] + p[1] * p[1]);
-    if (r <= g.bounds[g.n_vol] && fabs(p[2]) <= g.env[0]) return stack_of(g, r);
-    if (r <= g.world[0] && fabs(p[2]) <= g.world[1]) return 0;
-    return kOutside;
+    if ((r <= g.bounds[g.n_vol]) & (fabs(p[2]) <= g.env[0])) return stack_of_near(g, r, v0, v1);
+    return ((r <= g.world[0]) & (fabs(p[2]) <= g.world[1])) ? 0 : kOutside;
 }
 
 // ---- slabs ----------------------------------------------------------------
@@ -96,21 +108,21 @@ __device__ inline Hit slab_exit(const DevGeom& g, int v, const double p[3], cons
 #pragma clang fp contract(off)
     const double lo[3] = {-g.env[0], -g.env[1], g.bounds[v - 1]};
     const double hi[3] = {g.env[0], g.env[1], g.bounds[v]};
-    double bn = 1.0, bd = 0.0;    // nearest face so far at bn / bd; bd == 0: none yet
+    // nearest face so far at bn / bd.  The start (1 / 0) loses to any face:
+    // n * 0 < 1 * den for den > 0, so the first axis with motion is taken.
+    double bn = 1.0, bd = 0.0;
     double plane = hi[2];
     int face = 5;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0) continue;
         const bool up = d[a] > 0.0;
         const double n = up ? hi[a] - p[a] : p[a] - lo[a];
-        const double den = up ? d[a] : -d[a];
-        if (bd == 0.0 || n * bd < bn * den) {
-            bn = n;
-            bd = den;
-            face = 2 * a + (up ? 1 : 0);
-            plane = up ? hi[a] : lo[a];
-        }
+        const double den = fabs(d[a]);
+        const bool take = (d[a] != 0.0) & (n * bd < bn * den);
+        bn = take ? n : bn;
+        bd = take ? den : bd;
+        face = take ? 2 * a + (up ? 1 : 0) : face;
+        plane = take ? (up ? hi[a] : lo[a]) : plane;
     }
     const double best = bd > 0.0 ? bn / bd : kInf;
     Hit h;
@@ -137,31 +149,29 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
     const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
     // entry (max of near-plane distances) and exit (min of far-plane
     // distances) of the ray's parameter interval inside the envelope box
-    double nn = 0.0, nd = 0.0, fn = 0.0, fd = 0.0, plane = 0.0;
+    // The starts (-1 / 0 and 1 / 0) lose to any axis with motion (n * 0 >
+    // -den and n * 0 < den), so the first such axis is taken for both.
+    double nn = -1.0, nd = 0.0, fn = 1.0, fd = 0.0, plane = 0.0;
     int an = -1;
-    bool miss = false, have = false;
+    bool miss = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0) {
-            miss = miss || p[a] < lo[a] || p[a] > hi[a];
-            continue;
-        }
+        const bool moving = d[a] != 0.0;
         const bool up = d[a] > 0.0;
-        const double den = up ? d[a] : -d[a];
+        const double den = fabs(d[a]);
         const double n_near = up ? lo[a] - p[a] : p[a] - hi[a];
         const double n_far = up ? hi[a] - p[a] : p[a] - lo[a];
-        if (!have || n_near * nd > nn * den) {
-            nn = n_near;
-            nd = den;
-            an = a;
-            plane = up ? lo[a] : hi[a];
-        }
-        if (!have || n_far * fd < fn * den) {
-            fn = n_far;
-            fd = den;
-        }
-        have = true;
+        miss = miss | (!moving & ((p[a] < lo[a]) | (p[a] > hi[a])));
+        const bool tn = moving & (n_near * nd > nn * den);
+        const bool tf = moving & (n_far * fd < fn * den);
+        nn = tn ? n_near : nn;
+        nd = tn ? den : nd;
+        an = tn ? a : an;
+        plane = tn ? (up ? lo[a] : hi[a]) : plane;
+        fn = tf ? n_far : fn;
+        fd = tf ? den : fd;
     }
+    const bool have = nd != 0.0;
     Hit h;
     h.t = kInf;
     h.next = 0;
@@ -185,14 +195,12 @@ __device__ inline Hit slab_world(const DevGeom& g, const double p[3], const doub
     double wn = 1.0, wd = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0) continue;
         const bool up = d[a] > 0.0;
         const double n = up ? whi[a] - p[a] : p[a] - wlo[a];
-        const double den = up ? d[a] : -d[a];
-        if (wd == 0.0 || n * wd < wn * den) {
-            wn = n;
-            wd = den;
-        }
+        const double den = fabs(d[a]);
+        const bool take = (d[a] != 0.0) & (n * wd < wn * den);
+        wn = take ? n : wn;
+        wd = take ? den : wd;
     }
     double tw = wd > 0.0 ? wn / wd : kInf;
     tw = tw > 0.0 ? tw : 0.0;

@@ -717,7 +717,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
                                               uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks,
-                                              unsigned long long* lane_slots_lds)
+                                              unsigned long long* lane_slots_lds, bool vac_ok)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -735,10 +735,29 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         DepAcc acc{0.0, 0ull};
         int acc_vol = t.vol;
         for (; iters < inner;) {
-            const uint32_t ns = t.nstep;
-            step_track<P, INTEG>(c, t, o);
-            steps_here += o.did_step;
-            iters += 1;
+            uint32_t ns = t.nstep;
+            if (TY != kGamma && !INTEG && vac_ok && __all((t.vol == 0) & (acc_vol == 0))) {
+                // A wavefront whose charged tracks are all in the vacuum world
+                // (the loopers of a transport's low-population tail) steps
+                // them in the vacuum form of the step.  A step that leaves its
+                // track alive in the vacuum changes nothing but the track (no
+                // deposit, process, secondary, counter or ledger entry), so
+                // such steps repeat here with only the step count and the
+                // trace; the step that ends otherwise takes the bookkeeping
+                // below like any other.
+                for (;;) {
+                    step_track<P, false, true>(c, t, o);
+                    steps_here += o.did_step;
+                    iters += 1;
+                    if (o.status != kAlive || t.vol != 0 || iters >= inner) break;
+                    if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
+                    ns = t.nstep;
+                }
+            } else {
+                step_track<P, INTEG>(c, t, o);
+                steps_here += o.did_step;
+                iters += 1;
+            }
             if (TY != kGamma) {
                 rks.acc += (uint32_t)o.rk.acc;
                 rks.rej += (uint32_t)o.rk.rej;
@@ -849,6 +868,7 @@ k_step_batched(BatchArgs<P> A)
     const uint32_t participants = baskets < gridDim.x ? (baskets > 0 ? baskets : 1u) : gridDim.x;
     if (blockIdx.x >= participants) return;
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
+    const bool vac_ok = c_geom.field_map == kMapUniform;
     uint32_t steps_g = 0, steps_e = 0, steps_p = 0;
     uint32_t loads = 0, stores = 0;
     RkSum rks{0u, 0u, 0u};
@@ -864,13 +884,13 @@ k_step_batched(BatchArgs<P> A)
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
                 process_chunk<P, kGamma, BLOCK, STABLE, INTEG>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
-                                                loads, stores, n_chunks, rks, &rk_lds[3]);
+                                                loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
             else if (chunk < c0 + c1)
                 process_chunk<P, kElectron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
-                                                   steps_e, loads, stores, n_chunks, rks, &rk_lds[3]);
+                                                   steps_e, loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
             else
                 process_chunk<P, kPositron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
-                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks, &rk_lds[3]);
+                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);

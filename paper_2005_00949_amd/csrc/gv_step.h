@@ -186,10 +186,11 @@ __device__ inline bool stage_prestep(const Ctx<P>& c, Track<P>& t, StepOut<R>& o
 }
 
 // ---- ComputeIntLen ------------------------------------------------------
-template <class P, class R = typename P::R>
+// VAC: the track is known to be in the vacuum world (volume 0)
+template <class P, bool VAC = false, class R = typename P::R>
 __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>& L)
 {
-    const int m = vol_material(*c.g, t.vol);
+    const int m = VAC ? -1 : vol_material(*c.g, t.vol);
     L.m = m;
     L.sa = (R)0;
     L.stot = (R)0;
@@ -218,23 +219,25 @@ __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>
 }
 
 // ---- GeomQuery ----------------------------------------------------------
-template <class P, class R = typename P::R>
+template <class P, bool VAC = false, class R = typename P::R>
 __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 {
+    const int v = VAC ? 0 : t.vol;
     const double d[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
-    const Hit h = distance_out(*c.g, t.vol, t.x, d);
+    const Hit h = distance_out(*c.g, v, t.x, d);
     G.d_bnd = h.t;
     G.next = h.next;
     G.snap_axis = h.snap_axis;
     G.snap_val = h.snap_val;
-    G.safety = safety(*c.g, t.vol, t.x);
+    G.safety = safety(*c.g, v, t.x);
 }
 
 // ---- Propagation --------------------------------------------------------
 // INTEG = false compiles the straight line and the helix only (field_method
 // HELIX); INTEG = true adds the RK4 and RK45 integrators, which run in double
-// in both precision policies.
-template <class P, bool INTEG, class R = typename P::R>
+// in both precision policies.  VAC (vacuum world, uniform field) leaves out
+// the field-map evaluation.
+template <class P, bool INTEG, bool VAC = false, class R = typename P::R>
 __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
 #pragma clang fp contract(off)
@@ -250,7 +253,7 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     // the field at the pre-step point: its direction and kKB |B|
     double Bm = g.Bmag, kB = g.kB;
     double bh[3] = {g.Bhat[0], g.Bhat[1], g.Bhat[2]};
-    if (t.type != kGamma && g.field_map == kMapSolenoid) {
+    if (!VAC && t.type != kGamma && g.field_map == kMapSolenoid) {
         // in double: the helix phase is kB s / p (see rk4_map_move)
         double Bd[3];
         field_at<double>(g, t.x, Bd);
@@ -321,7 +324,7 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     } else {
         helix_move<R>(t.type, t.T, bh, kB, pr.s, t.x, t.u);
     }
-    const int nv = locate(g, t.x);
+    const int nv = locate(g, t.x, t.vol, G.next);
     if (nv != t.vol) {
         t.vol = nv;
         pr.lim = kLimGeom;
@@ -509,17 +512,22 @@ __device__ inline void stage_finish(const Ctx<P>& c, Track<P>& t, const Limits<R
 }
 
 // ---- the whole step in registers ----------------------------------------
-template <class P, bool INTEG, class R = typename P::R>
+// VAC: specialisation for a charged track in the vacuum world of a uniform
+// field with the helix (the caller checks this).  It runs the same stage code
+// with the material branches decided at compile time, so it takes exactly the
+// steps of the general form.
+template <class P, bool INTEG, bool VAC = false, class R = typename P::R>
 __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
 {
+    static_assert(!(VAC && INTEG), "the vacuum form is helix-only");
     init_out(t, o);
     if (!stage_prestep(c, t, o)) return;
     Limits<R> L;
-    stage_limit(c, t, L);
+    stage_limit<P, VAC>(c, t, L);
     Geo G;
-    stage_geom(c, t, G);
+    stage_geom<P, VAC>(c, t, G);
     Prop<R> pr;
-    stage_move<P, INTEG>(c, t, L, G, pr);
+    stage_move<P, INTEG, VAC>(c, t, L, G, pr);
     o.did_step = 1;
     o.s = pr.s;
     o.lim = pr.lim;
