@@ -736,20 +736,34 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         int acc_vol = t.vol;
         for (; iters < inner;) {
             uint32_t ns = t.nstep;
-            if (TY != kGamma && !INTEG && vac_ok && __all((t.vol == 0) & (acc_vol == 0))) {
-                // A wavefront whose charged tracks are all in the vacuum world
-                // (the loopers of a transport's low-population tail) steps
-                // them in the vacuum form of the step.  A step that leaves its
-                // track alive in the vacuum changes nothing but the track (no
-                // deposit, process, secondary, counter or ledger entry), so
-                // such steps repeat here with only the step count and the
-                // trace; the step that ends otherwise takes the bookkeeping
-                // below like any other.
+            const bool acc_empty = (acc.e == 0.0) & (acc.x == 0ull);
+            if (TY != kGamma && !INTEG && vac_ok && __all((t.vol == 0) & acc_empty)) {
+                // A wavefront whose charged tracks are all in volumes without
+                // material (the loopers of a transport's low-population tail)
+                // steps them in the vacuum form of the step, here in the world
+                // volume and below in vacuum layers.  A step that leaves its
+                // track alive in vacuum changes nothing but the track (no
+                // deposit, process, secondary, counter or ledger entry; the
+                // deposit accumulator stays empty, so its volume does not
+                // matter), so such steps repeat with only the step count and
+                // the trace; the step that ends otherwise takes the
+                // bookkeeping below like any other.
+                for (;;) {
+                    step_track<P, false, true, true>(c, t, o);
+                    steps_here += o.did_step;
+                    iters += 1;
+                    if (o.status != kAlive || t.vol != 0 || iters >= inner) break;
+                    if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
+                    ns = t.nstep;
+                }
+            } else if (TY != kGamma && !INTEG && vac_ok &&
+                       __all((vol_material(c_geom, t.vol) < 0) & acc_empty)) {
                 for (;;) {
                     step_track<P, false, true>(c, t, o);
                     steps_here += o.did_step;
                     iters += 1;
-                    if (o.status != kAlive || t.vol != 0 || iters >= inner) break;
+                    if (o.status != kAlive || iters >= inner) break;
+                    if (t.vol != o.vol_pre && vol_material(c_geom, t.vol) >= 0) break;
                     if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
                     ns = t.nstep;
                 }

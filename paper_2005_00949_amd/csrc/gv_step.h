@@ -186,7 +186,7 @@ __device__ inline bool stage_prestep(const Ctx<P>& c, Track<P>& t, StepOut<R>& o
 }
 
 // ---- ComputeIntLen ------------------------------------------------------
-// VAC: the track is known to be in the vacuum world (volume 0)
+// VAC: the track is known to be in a volume without material
 template <class P, bool VAC = false, class R = typename P::R>
 __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>& L)
 {
@@ -219,10 +219,11 @@ __device__ inline void stage_limit(const Ctx<P>& c, const Track<P>& t, Limits<R>
 }
 
 // ---- GeomQuery ----------------------------------------------------------
-template <class P, bool VAC = false, class R = typename P::R>
+// WORLD: the track is known to be in the world volume
+template <class P, bool WORLD = false, class R = typename P::R>
 __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 {
-    const int v = VAC ? 0 : t.vol;
+    const int v = WORLD ? 0 : t.vol;
     const double d[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
     const Hit h = distance_out(*c.g, v, t.x, d);
     G.d_bnd = h.t;
@@ -235,8 +236,8 @@ __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 // ---- Propagation --------------------------------------------------------
 // INTEG = false compiles the straight line and the helix only (field_method
 // HELIX); INTEG = true adds the RK4 and RK45 integrators, which run in double
-// in both precision policies.  VAC (vacuum world, uniform field) leaves out
-// the field-map evaluation.
+// in both precision policies.  VAC (a volume without material in a uniform
+// field) leaves out the field-map evaluation.
 template <class P, bool INTEG, bool VAC = false, class R = typename P::R>
 __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
@@ -512,11 +513,12 @@ __device__ inline void stage_finish(const Ctx<P>& c, Track<P>& t, const Limits<R
 }
 
 // ---- the whole step in registers ----------------------------------------
-// VAC: specialisation for a charged track in the vacuum world of a uniform
-// field with the helix (the caller checks this).  It runs the same stage code
+// VAC: specialisation for a charged track in a volume without material (the
+// world or a vacuum layer) in a uniform field with the helix (the caller
+// checks this); WORLD: in the world volume.  It runs the same stage code
 // with the material branches decided at compile time, so it takes exactly the
 // steps of the general form.
-template <class P, bool INTEG, bool VAC = false, class R = typename P::R>
+template <class P, bool INTEG, bool VAC = false, bool WORLD = false, class R = typename P::R>
 __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
 {
     static_assert(!(VAC && INTEG), "the vacuum form is helix-only");
@@ -525,7 +527,7 @@ __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
     Limits<R> L;
     stage_limit<P, VAC>(c, t, L);
     Geo G;
-    stage_geom<P, VAC>(c, t, G);
+    stage_geom<P, WORLD>(c, t, G);
     Prop<R> pr;
     stage_move<P, INTEG, VAC>(c, t, L, G, pr);
     o.did_step = 1;
