@@ -657,8 +657,12 @@ template <> QueueMem<P64>& batch_queues<P64>() { return L.q64; }
 template <> QueueMem<PMix>& batch_queues<PMix>() { return L.qmix; }
 
 // capture K launches alternating parity (K even: a replay ends where it began)
+// vacuum steps per track and helper launch in the tail replays
+constexpr int kVacHelperSteps = 4096;
+
 template <class P>
-int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, hipGraph_t* g, hipGraphExec_t* ge)
+int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, bool helper, hipGraph_t* g,
+            hipGraphExec_t* ge)
 {
     QueueMem<P>& Q = batch_queues<P>();
     hipStream_t s = stream();
@@ -681,7 +685,10 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, h
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
-    for (int k = 0; k < K; ++k) launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
+    for (int k = 0; k < K; ++k) {
+        if (helper) k_vacuum_helper<P><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
+        launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
+    }
     hipError_t ce = hipStreamEndCapture(s, g);
     if (ce != hipSuccess) return fail(GV_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
     HIPCHK(hipGraphInstantiate(ge, *g, nullptr, nullptr, 0));
@@ -691,9 +698,11 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, h
 template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
 {
     drop_graph();
-    int rc = capture<P>(tu, tu.occupancy * L.n_cu, tu.K, tu.inner_bulk, tu.inner_tail, &L.graph, &L.gexec);
+    int rc = capture<P>(tu, tu.occupancy * L.n_cu, tu.K, tu.inner_bulk, tu.inner_tail, false, &L.graph, &L.gexec);
     if (rc) return rc;
-    rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, &L.graph_tail, &L.gexec_tail);
+    // the vacuum helper serves the helix in a uniform field (its step form)
+    const bool helper = L.cfg.field_method == GV_FIELD_HELIX && L.geom.field_map == kMapUniform;
+    rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, helper, &L.graph_tail, &L.gexec_tail);
     if (rc) return rc;
     L.gkey = key;
     return GV_OK;

@@ -136,3 +136,25 @@ def test_vacuum_loopers_mixed_ledger(gv, oracle_mod, case):
     rhs = edep.sum(1) + L[:, 0] + L[:, 1]
     assert np.max(np.abs(lhs - rhs) / lhs) < 1e-5
     assert st["killed"] == ref["counters"]["killed"]
+
+
+def test_tail_replays_equal_plain_on_full_barrel(gv):
+    """c5 at full size (2,000 events in the barrel, 3.8 T): the batched FP64
+    driver passes its population peak and ends in the tail replays, where the
+    vacuum helper kernel steps the last loopers of the beam pipe; its
+    fixed-point deposits, ledger and step counts equal the plain driver's
+    (which has neither) bit for bit."""
+    geom, prim, seed = gv_inputs.workload("c5", None)
+    runs = {}
+    for drv in ("plain", "batched"):
+        eng = gv.Engine(geom, precision=gv.P64, deposit_mode=gv.DEPOSIT_FIXED,
+                        driver=gv.DRIVER_PLAIN if drv == "plain" else gv.DRIVER_BATCHED)
+        edep = eng.transport(prim, seed)
+        runs[drv] = (edep, eng.ledger(), eng.stats())
+        eng.close()
+    (e_p, l_p, s_p), (e_b, l_b, s_b) = runs["plain"], runs["batched"]
+    print(f"\n[c5 full] steps {s_b['total_steps']}, killed {s_b['killed']}, tail kernel {s_b['tail_kernel_ms']:.0f} ms")
+    assert s_b["tail_kernel_ms"] > 0.0 and s_b["killed"] >= 1
+    assert s_b["total_steps"] == s_p["total_steps"] and list(s_b["steps"]) == list(s_p["steps"])
+    assert s_b["killed"] == s_p["killed"] and s_b["escaped"] == s_p["escaped"]
+    assert np.array_equal(e_b, e_p) and np.array_equal(l_b, l_p)
