@@ -520,6 +520,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": "k_step_batched<PMix,%d>" % min(st0["basket"], 256),
+                     "launch": "one step kernel launch; in the low-population tail replays the one-workgroup "
+                               "k_vacuum_helper before it is part of the launch",
                      "avg_launch_us": avg_launch_s * 1e6, "alg_bytes_per_launch": bytes_per_launch,
                      "steps_per_launch": steps_per_launch, "launches": res["launches"],
                      "kernel_source_sha1": kernel_source_hash()},
