@@ -73,15 +73,11 @@ static void solenoid_field(double B0, double R, double L, const double x[3], dou
     double f0 = 2.0 * L / sqrt(R2 + L * L);
     double c = B0 / f0;
     double a = x[2] + L, b = x[2] - L;
-    double sa = sqrt(R2 + a * a), sb = sqrt(R2 + b * b);
-    /* ia = 1/sqrt(R^2 + a^2), ib likewise, from one division */
-    double r = 1.0 / (sa * sb);
-    double ia = sb * r, ib = sa * r;
-    double ia2 = ia * ia, ib2 = ib * ib;
-    double ia3 = ia2 * ia, ib3 = ib2 * ib;
-    double g = c * (a * ia - b * ib);
-    double g1 = c * R2 * (ia3 - ib3);                           /* g'  */
-    double g2 = -3.0 * c * R2 * (a * (ia3 * ia2) - b * (ib3 * ib2));  /* g'' */
+    double qa = R2 + a * a, qb = R2 + b * b;
+    double sa = sqrt(qa), sb = sqrt(qb);
+    double g = c * (a / sa - b / sb);
+    double g1 = c * R2 * (1.0 / (qa * sa) - 1.0 / (qb * sb));               /* g'  */
+    double g2 = -3.0 * c * R2 * (a / (qa * qa * sa) - b / (qb * qb * sb));  /* g'' */
     double r2 = x[0] * x[0] + x[1] * x[1];
     out[0] = -0.5 * x[0] * g1;
     out[1] = -0.5 * x[1] * g1;
@@ -200,9 +196,8 @@ static void dp_deriv(const or_field* f, double kq, const double y[6], double k[6
  *   substep with err <= tol/16 (the position part scales as h^4), never past
  *   the end of the interval.  Powers of two keep every substep length an
  *   exact function of s and theta, so any two IEEE implementations take the
- *   same substeps.  Stops after max_sub attempts.  Sums over stages run in
- *   stage order as fused multiply-adds (fma), as does the stage point
- *   y + h sum. */
+ *   same substeps.  Stops after max_sub attempts.  Stage sums are the plain
+ *   sums of the tableau rows, in stage order. */
 #define RK45_K 8.1e-4
 int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, double tol,
                      int32_t max_sub, double pos[3], double dir[3], double* s_done, int32_t* n_rej)
@@ -230,17 +225,17 @@ int32_t or_rk45_move(int32_t type, double ekin, const or_field* f, double s, dou
         dp_deriv(f, kq, y, k[0]);
         for (int i = 1; i < 7; ++i) {
             for (int c = 0; c < 6; ++c) {
-                double sum = DP_A[i][0] * k[0][c];
-                for (int j = 1; j < i; ++j) sum = fma(DP_A[i][j], k[j][c], sum);
-                yi[c] = fma(h, sum, y[c]);
+                double sum = 0.0;
+                for (int j = 0; j < i; ++j) sum += DP_A[i][j] * k[j][c];
+                yi[c] = y[c] + h * sum;
             }
             dp_deriv(f, kq, yi, k[i]);
         }
         /* yi now holds the 5th-order solution (the last row equals DP_B) */
         double err = 0.0;
         for (int c = 0; c < 6; ++c) {
-            double e = (DP_B[0] - DP_BH[0]) * k[0][c];
-            for (int j = 1; j < 7; ++j) e = fma(DP_B[j] - DP_BH[j], k[j][c], e);
+            double e = 0.0;
+            for (int j = 0; j < 7; ++j) e += (DP_B[j] - DP_BH[j]) * k[j][c];
             if (c >= 3) e = h * e;
             if (fabs(e) > err) err = fabs(e);
         }
