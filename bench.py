@@ -69,10 +69,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def paired_layers(x, y):
+def paired_layers(x, y, gate=True):
     """Per-layer paired comparison of deposits X (tested) vs Y (reference):
     mean difference within 3 sigma of the paired differences and within 0.5%
-    on layers that hold at least 1% of the mean total deposit."""
+    on layers that hold at least 1% of the mean total deposit.  With
+    gate=False (two different samplers, whose histories decorrelate) the
+    statistics are reported without a verdict, together with the 3-sigma
+    resolution of the sample on the big layers."""
     import numpy as np
     d = x - y
     n = len(d)
@@ -83,8 +86,12 @@ def paired_layers(x, y):
     ok3 = np.abs(delta) <= 3 * sig + 1e-9 * np.abs(m)
     ok05 = ~big | (np.abs(delta) <= 0.005 * np.abs(m))
     worst = float(np.max(np.abs(delta[big]) / m[big])) if big.any() else 0.0
-    return dict(pass_=bool(ok05.all() and (~ok3).sum() <= max(1, len(m) // 20)),
-                worst_rel_big_layers=worst, layers_outside_3sigma=int((~ok3).sum()), layers=int(len(m)))
+    out = dict(worst_rel_big_layers=worst, layers_outside_3sigma=int((~ok3).sum()), layers=int(len(m)),
+               three_sigma_rel_median_big_layers=float(np.median(3 * sig[big] / m[big])) if big.any() else 0.0,
+               events=int(n))
+    if gate:
+        out["pass_"] = bool(ok05.all() and (~ok3).sum() <= max(1, len(m) // 20))
+    return out
 
 
 def run_gpu(args):
@@ -123,6 +130,7 @@ def run_gpu(args):
     alg_bytes = 0.0
     edep_first = None
     per_ms, tail_ms = [], []
+    tail_steps, kern_ms = 0, []
     t0 = time.perf_counter()
     for k in range(args.steps):
         eng.transport_staged(seed + k, edep.data_ptr())
@@ -135,6 +143,8 @@ def run_gpu(args):
         alg_bytes += st["alg_bytes"]
         per_ms.append(st["transport_ms"])
         tail_ms.append(st["tail_kernel_ms"])
+        tail_steps += st["tail_steps"]
+        kern_ms.append(st["kernel_ms"])
         if k == 0:
             edep_first = edep.cpu().numpy()
             st0 = st
@@ -144,7 +154,8 @@ def run_gpu(args):
     elapsed = time.perf_counter() - t0
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
                alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
-               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots, warm_ms=warm_ms)
+               autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots, warm_ms=warm_ms,
+               tail_steps=tail_steps, kern_ms=kern_ms, edep_first=edep_first)
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
@@ -177,7 +188,10 @@ def run_gpu(args):
             ttail.append(round(st["tail_kernel_ms"], 2))
         tables = dict(steps_per_s=tsteps / sum(tt), median_ms_per_transport=float(np.median(tt)) * 1e3,
                       ms_per_transport=[round(x * 1e3, 2) for x in tt], tail_ms_per_transport=ttail,
-                      edep_vs_rejection=paired_layers(edep_tab, edep_first))
+                      edep_vs_rejection=paired_layers(edep_tab, edep_first, gate=False),
+                      note="table and rejection sampling draw different final states from the same "
+                           "streams, so the histories decorrelate after the first interaction: the "
+                           "per-layer comparison is reported, not gated")
         log(f"[bench] table sampling: {tables['steps_per_s']:.3g} steps/s")
         eng.configure(fs_alias=0)
 
@@ -278,7 +292,7 @@ def run_testem5(args, gv, torch, cfg):
                photons_forward=float(h[0, :, 10:].sum() / n), photons_backward=float(h[0, :, :10].sum() / n))
     if not args.no_cpu:
         import oracle
-        r = oracle.Oracle(geom).transport(prim, seed, n_threads=max(1, min(os.cpu_count() or 1, 16)))["escape_hist"]
+        r = oracle.Oracle(geom).transport(prim, seed, n_threads=host_cpus()["threads"])["escape_hist"]
         out["oracle"] = dict(electrons_forward=float(r[1, :, 10:].sum() / n),
                              electrons_backward=float(r[1, :, :10].sum() / n),
                              photons_forward=float(r[0, :, 10:].sum() / n), photons_backward=float(r[0, :, :10].sum() / n))
@@ -369,33 +383,76 @@ def run_field_map(args, gv, torch, cfg):
     return out
 
 
+def host_cpus():
+    """CPUs this process may run on, the pool size of the CPU legs (at most
+    16: the host share of one GPU on a shared box), and the host's core count
+    from lscpu."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    lscpu = {}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                lscpu[k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+
+    def num(k):
+        try:
+            return int(lscpu.get(k, "").split()[0])
+        except (ValueError, IndexError):
+            return None
+    cores = None
+    if num("Core(s) per socket") and num("Socket(s)"):
+        cores = num("Core(s) per socket") * num("Socket(s)")
+    return dict(available=avail, threads=max(1, min(avail, 16)), lscpu_cpus=num("CPU(s)"), lscpu_cores=cores,
+                model=lscpu.get("Model name") or cpu_model())
+
+
 def run_cpu_baseline(args):
+    """The FP64 oracle on the host: the whole batch of the timed workload when
+    it fits the time budget (then its deposits also serve as the reference of
+    the paired per-layer test of the headline), else the first events; plus a
+    single-thread rate on a small sample."""
     import numpy as np
 
     import gv_inputs
     import oracle
     geom, prim, seed = gv_inputs.workload(args.workload, args.events)
-    sample = prim[prim["event"] < args.cpu_events]
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    cpus = host_cpus()
+    threads = cpus["threads"]
     o = oracle.Oracle(geom)
-    t = time.perf_counter()
-    r = o.transport(sample, seed, n_threads=threads)
-    dt = time.perf_counter() - t
-    c = r["counters"]
-    steps = c["steps_gamma"] + c["steps_electron"] + c["steps_positron"]
-    # one thread on a tenth of the sample, for the per-core rate
+    # single thread on the first events, for the per-core rate and the budget
     small = prim[prim["event"] < max(1, args.cpu_events // 10)]
     t = time.perf_counter()
     r1 = o.transport(small, seed, n_threads=1)
     dt1 = time.perf_counter() - t
     c1 = r1["counters"]
     steps1 = c1["steps_gamma"] + c1["steps_electron"] + c1["steps_positron"]
-    return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
-                sample=f"first {args.cpu_events} events of the same batch ({len(sample)} primaries, "
-                       f"{steps} steps, {dt:.1f} s, FP64 history-based, {threads} threads)",
-                primaries_per_s=len(sample) / dt, cpu_model=cpu_model(),
-                single_thread_steps_per_s=steps1 / dt1,
-                single_thread_sample=f"first {len(small)} events, {steps1} steps, {dt1:.1f} s")
+    rate1 = steps1 / dt1
+    n_events = int(prim["event"].max()) + 1
+    est_steps = steps1 / len(small) * len(prim)
+    est_s = est_steps / (rate1 * threads * 0.6)
+    full = args.cpu_full and est_s <= args.cpu_budget_s
+    sample = prim if full else prim[prim["event"] < args.cpu_events]
+    log(f"[bench] CPU oracle: {'whole batch' if full else f'first {args.cpu_events} events'} on {threads} threads "
+        f"(estimate for the whole batch {est_s:.0f} s)")
+    t = time.perf_counter()
+    r = o.transport(sample, seed, n_threads=threads)
+    dt = time.perf_counter() - t
+    c = r["counters"]
+    steps = c["steps_gamma"] + c["steps_electron"] + c["steps_positron"]
+    what = f"the whole batch ({n_events} events" if full else f"first {args.cpu_events} events of the same batch ("
+    out = dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
+               sample=f"{what}, {len(sample)} primaries, {steps} steps, {dt:.1f} s, FP64 history-based, "
+                      f"{threads} threads)",
+               primaries_per_s=len(sample) / dt, cpu_model=cpus["model"], host_cpus_lscpu=cpus["lscpu_cpus"],
+               host_cores_lscpu=cpus["lscpu_cores"], cpus_available=cpus["available"],
+               single_thread_steps_per_s=rate1,
+               single_thread_sample=f"first {len(small)} events, {steps1} steps, {dt1:.1f} s")
+    return out, (r["edep"] if full else None)
 
 
 def cpu_model():
@@ -443,7 +500,11 @@ def main():
     ap.add_argument("--table-steps", type=int, default=3,
                     help="timed transports with table (alias) final-state sampling")
     ap.add_argument("--fp64-batched", type=int, default=1)
-    ap.add_argument("--cpu-events", type=int, default=600)
+    ap.add_argument("--cpu-events", type=int, default=600,
+                    help="events of the CPU oracle sample when the whole batch does not fit the budget")
+    ap.add_argument("--cpu-full", type=int, default=1, help="run the CPU oracle on the whole batch if it fits")
+    ap.add_argument("--cpu-budget-s", type=float, default=60.0,
+                    help="estimated wall time up to which the CPU oracle runs the whole batch")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcie", action="store_true", help="skip the host-buffer (PCIe-inclusive) transport")
     ap.add_argument("--out", default=None)
@@ -459,7 +520,11 @@ def main():
         sys.exit(2)
 
     res, plain, b64 = run_gpu(args)
-    cpu = None if args.no_cpu else run_cpu_baseline(args)
+    cpu, edep_oracle = (None, None) if args.no_cpu else run_cpu_baseline(args)
+    # the headline's matched-edep check against the FP64 oracle itself: the
+    # first timed transport (same primaries and seed) against the oracle's
+    # deposits, paired per layer
+    vs_oracle = paired_layers(res["edep_first"], edep_oracle) if edep_oracle is not None else None
 
     value = res["steps"] / res["elapsed"]
     ms = res["elapsed"] / args.steps * 1e3
@@ -509,6 +574,13 @@ def main():
         "pcie_inclusive": {"ms_per_transport": res["pcie_inclusive_ms"],
                            "steps_per_s": res["pcie_inclusive_steps_per_s"]},
         "track_steps_per_transport": res["steps"] / args.steps,
+        # the two phases of a transport: the shower (population above the
+        # tail threshold) and the low-population tail of looping tracks
+        "shower_steps_per_s": ((res["steps"] - res["tail_steps"]) /
+                               max((sum(res["kern_ms"]) - sum(res["tail_ms"])) * 1e-3, 1e-12)),
+        "tail_fraction": sum(res["tail_ms"]) / max(sum(res["per_ms"]), 1e-12),
+        "tail_steps_per_transport": res["tail_steps"] / args.steps,
+        "edep_vs_oracle": vs_oracle,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (value / plain["steps_per_s"]) if plain else None,
         "batched_fp64": b64,

@@ -235,6 +235,7 @@ typedef struct {
                                        wavefronts of every basket, a wavefront running as many
                                        iterations as its busiest lane; total steps / lane_slots is
                                        the lane use of the stepping loop (0 for the plain driver) */
+    int64_t tail_steps;             /* steps taken in the launches counted in tail_kernel_ms */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */
@@ -246,64 +247,126 @@ typedef struct {
     double ekin, edep, step;
 } gv_trace_rec;
 
-/* Set up materials, geometry and tables on the current HIP device; replaces
- * any previous context.  Errors: GV_E_INVALID_ARG, GV_E_GEOMETRY,
- * GV_E_TABLES, GV_E_HIP. */
+/* gv_init -- set up materials, geometry and tables (the detector
+ * description and physics tables that every stage reads: geometry of
+ * Sec. 3.2 / 3.4 for a layered stack, the per-material cross-section,
+ * stopping-power and range tables of Sec. 3.5's models).
+ *   mats[n_mats]: host array, 1 <= n_mats <= GV_MAX_MATS; copied.
+ *   geom: host record; its arrays are copied.  Validated: stack bounds
+ *     strictly increasing and finite, material / cell ids in range, every
+ *     material volume scored, envelope inside the world, field finite (a
+ *     solenoid needs B along z and a positive radius and half-length).
+ *   tables: the grid and thresholds from which the library builds every
+ *     table on the device in FP64 (FP32 copies for the mixed policy).  The
+ *     caller passes a grid, not table contents: the device computes the
+ *     tables from the same closed forms as any other implementation would,
+ *     so no table blob crosses the boundary.
+ * Binds the context to the current HIP device and replaces any previous
+ * context (and its staged batch).  Nothing is retained from the caller.
+ * Errors: GV_E_INVALID_ARG (null pointer, count out of range, material
+ * fractions), GV_E_GEOMETRY, GV_E_TABLES (grid, cuts, or a non-finite /
+ * non-positive built value), GV_E_HIP, GV_E_STATE (called during a
+ * transport).  On error no context remains. */
 int gv_init(const gv_material* mats, int32_t n_mats, const gv_geometry* geom,
             const gv_tables* tables);
 
-/* Replace the run options (validated; GV_E_INVALID_ARG on bad values). */
+/* gv_configure -- replace the run options (host record, copied): driver
+ * (per-stage plain FP64 stepping of Sec. 2.1.2, or the batched persistent
+ * kernel over per-type queues that stands in for the scheduler of
+ * Sec. 2.1.1), precision policy, basket / occupancy / inner steps (0 =
+ * autotuned), field method (Sec. 3.6), stream, capacity, events in flight,
+ * queue order, deposit mode (Sec. 5.1 reproducibility) and table sampling
+ * per model (Sec. 3.5).  Every field is validated before any is applied.
+ * Errors: GV_E_INVALID_ARG (null, out-of-range or reserved field set),
+ * GV_E_NOT_INIT, GV_E_STATE; on error the previous options stay. */
 int gv_configure(const gv_config* cfg);
 
-/* Transport n primaries with run seed `seed` and score deposits.
- * edep_out: E x n_cells doubles, row-major [event][cell], MeV; host memory
- * unless edep_on_device.  Zero-filled, then accumulated; complete on return.
- * Random numbers: Philox4x32-10 keyed by the seed, counter (event, track id,
- * step, purpose) (the per-track streams of Sec. 5.1).  Errors:
- * GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_CAPACITY, GV_E_HIP, GV_E_STATE. */
+/* gv_transport -- transport n primaries (the event server's injection,
+ * Sec. 2.1 and 3.7.1) through every stage of Sec. 2.1.2 until all tracks
+ * have stopped, escaped or reached the looper cap, and score the energy each
+ * event deposits in each cell (per-event scoring of Sec. 3.8.1).
+ *   primaries[n]: host array of gv_primary, copied; n >= 1.  Events are
+ *     0..E-1 with E = 1 + max(event); a primary's order of appearance within
+ *     its event is its track id.  Validation as for gv_stage.
+ *   seed: run seed of the counter-based streams: Philox4x32-10 keyed by the
+ *     seed, counter (event, track id, step, purpose) (the per-track streams
+ *     of Sec. 5.1), so results do not depend on batching or scheduling.
+ *   edep_out: caller-owned E x n_cells doubles, row-major [event][cell], in
+ *     MeV; host memory unless gv_config.edep_on_device (then a device
+ *     pointer on the library's device, written on the configured stream).
+ *     Zero-filled, then accumulated; complete when the call returns.
+ * Errors: GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_CAPACITY (queues overflow
+ * with one event in flight), GV_E_HIP, GV_E_STATE (re-entered, or the step
+ * loop exceeded its launch bound).  On error edep_out is unspecified and the
+ * counters of gv_stats describe the failed call. */
 int gv_transport(const gv_primary* primaries, int64_t n, uint64_t seed, double* edep_out);
 
-/* The same transport in two calls, so that the primaries can be made
- * resident on the device once and transported many times (e.g. with
- * different seeds or options): gv_stage validates the primaries (same rules
- * and errors as gv_transport), groups them by event and copies them to the
- * device; gv_transport_staged transports the staged batch (errors as
- * gv_transport, plus GV_E_STATE if nothing is staged).  gv_init discards the
- * staged batch. */
+/* gv_stage / gv_transport_staged -- the same transport in two calls, so that
+ * the primaries are made resident on the device once (the event server's
+ * input buffer, Sec. 3.7.1) and transported many times with different seeds
+ * or options.  gv_stage validates the primaries (pdg 11, -11 or 22; event
+ * >= 0; 0 < ekin <= last table node; finite position; |dir| within 1e-6 of
+ * 1), groups them by event (stable) and copies them to the device; the
+ * caller's array is not retained.  gv_transport_staged transports the staged
+ * batch; seed and edep_out as for gv_transport.  gv_init discards the staged
+ * batch.  Errors: as gv_transport, plus GV_E_STATE if nothing is staged. */
 int gv_stage(const gv_primary* primaries, int64_t n);
 int gv_transport_staged(uint64_t seed, double* edep_out);
 
-/* Counters of the last transport. */
+/* gv_stats -- counters of the last transport (the quantities the paper's
+ * validation and performance sections report: steps and secondaries per
+ * type, interactions per process, Sec. 4; stepping time, basket and
+ * occupancy, Sec. 6.2; integration work and idle lanes, Sec. 3.6), copied
+ * into the caller-owned *out.  Errors: GV_E_INVALID_ARG (null),
+ * GV_E_NOT_INIT. */
 int gv_stats(gv_stats_t* out);
 
-/* Per-event ledger of the last transport: n_events x 4 doubles
- * (escaped energy, killed energy, conversions, annihilations). */
+/* gv_ledger -- per-event energy ledger of the last transport (energy that
+ * left the scored cells: escaped and killed energy, and the conversion and
+ * annihilation counts that change the rest-mass balance), so that
+ *   sum T_primaries + 2 m (annihilations - conversions)
+ *     = sum edep + escaped + killed   per event.
+ * out: caller-owned n_events x 4 doubles (escaped MeV, killed MeV,
+ * conversions, annihilations); n_events must equal the last transport's.
+ * Errors: GV_E_INVALID_ARG, GV_E_NOT_INIT. */
 int gv_ledger(double* out, int64_t n_events);
 
-/* Step records of the last transport (trace_cap > 0); *n_out = records copied. */
+/* gv_trace -- step records of the last transport (trace_cap > 0): one
+ * record per propagation, the per-track step history that the paper's
+ * reproducibility test compares (Sec. 5.1).  out: caller-owned, cap
+ * records; *n_out = records copied (records beyond trace_cap were dropped;
+ * order is not defined).  Errors: GV_E_INVALID_ARG, GV_E_NOT_INIT, GV_E_HIP. */
 int gv_trace(gv_trace_rec* out, int64_t cap, int64_t* n_out);
 
-/* Number of scoring cells of the current geometry. */
+/* gv_n_cells -- number of scoring cells of the current geometry (the row
+ * length of edep_out).  Errors: GV_E_INVALID_ARG, GV_E_NOT_INIT. */
 int gv_n_cells(int32_t* out);
 
-/* Particles that left the world in the last transport, counted per type
- * (gamma, e-, e+), kinetic-energy bin (5 per decade from 1 keV, 40 bins)
- * and bin of the direction cosine with +z (20 bins on [-1, 1]): the
- * transmission / reflection spectra of single-slab set-ups (Sec. 4).
+/* gv_escape_hist -- particles that left the world in the last transport,
+ * counted per type (gamma, e-, e+), kinetic-energy bin (5 per decade from
+ * 1 keV, 40 bins) and bin of the direction cosine with +z (20 bins on
+ * [-1, 1]): the transmission / reflection spectra of single-slab set-ups
+ * (Sec. 4).  Integer counts, so any arrival order gives the same histogram.
  * out: 3 x 40 x 20 uint64, row-major, caller-owned; n >= 2400.
- * GV_E_NOT_INIT, GV_E_INVALID_ARG. */
+ * Errors: GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_HIP. */
 int gv_escape_hist(uint64_t* out, int64_t n);
 
-/* Test access to the final-state table of one model (GV_FS_*) at one node
- * (0..120, energy 0.1 MeV * 10^(node/20)): the density at 65 points (p), the
- * 64 alias thresholds (q) and alias columns, and whether the node lies above
- * the model's threshold.  Caller-owned outputs.  GV_E_NOT_INIT,
- * GV_E_INVALID_ARG. */
+/* gv_alias_table -- test access to the final-state sampling table of one
+ * model (GV_FS_*) at one node (0..120, energy 0.1 MeV * 10^(node/20)): the
+ * sampling tables of Sec. 3.5, read back for comparison.  Outputs are
+ * caller-owned: p[65] (density of the transformed variable at 65 points),
+ * q[64] (alias thresholds), alias[64] (alias columns), *valid (node above
+ * the model's threshold).  Errors: GV_E_NOT_INIT, GV_E_INVALID_ARG, GV_E_HIP. */
 int gv_alias_table(int32_t model, int32_t node, double* p, double* q, int32_t* alias, int32_t* valid);
 
-/* Release device memory; the context must be re-initialised to be used. */
+/* gv_finalize -- release every device allocation and the staged batch; the
+ * context must be re-initialised before further use.  Does nothing while a
+ * transport is running. */
 void gv_finalize(void);
 
+/* gv_last_error -- human-readable message of the last nonzero status on the
+ * calling thread (thread-local storage owned by the library, valid until
+ * that thread's next call). */
 const char* gv_last_error(void);
 
 /* ---------------- test entry points ---------------- */
@@ -369,7 +432,24 @@ typedef struct {
     double* values;
 } gv_debug_io;
 
-/* Run one test stage on n inputs (GV_DBG_TABLE: n = number of nodes). */
+/* gv_debug_step -- test entry point: run one stage on n independent inputs
+ * given as host arrays (copied to the device and back; the caller owns
+ * every array in io):
+ *   GV_DBG_STEP    one complete step of Sec. 2.1.2 (PreStep, ComputeIntLen,
+ *                  GeomQuery, Propagation, PostPropagation, AlongStep,
+ *                  PostStep) on arbitrary track states, with the outputs of
+ *                  every stage (physics length, boundary distance, safety,
+ *                  limiter, step length, post-step state, deposit,
+ *                  secondaries), so that each stage's result can be checked
+ *                  on its own against an independent implementation;
+ *   GV_DBG_PHILOX  the counter-based generator of Sec. 3.3.2;
+ *   GV_DBG_COMPACT the queue compaction of the stage baskets (Sec. 2.1.1);
+ *   GV_DBG_TABLE   the built tables of Sec. 3.5;
+ *   GV_DBG_GEOM    the geometry queries of Sec. 3.4.
+ * GV_DBG_TABLE: n = number of nodes.  Uses temporary device allocations.
+ * Errors: GV_E_INVALID_ARG (unknown stage, null or invalid inputs),
+ * GV_E_NOT_INIT, GV_E_STATE (during a transport, or a look-back wait gave
+ * up), GV_E_HIP. */
 int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io);
 
 #ifdef __cplusplus

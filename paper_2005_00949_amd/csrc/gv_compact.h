@@ -25,9 +25,10 @@ constexpr uint64_t kFlagAgg = 1ull, kFlagInc = 2ull;
 // bound on the polls of one look-back window (each poll sleeps ~64 cycles);
 // past it the error flag is raised and the launch completes with a wrong count
 constexpr uint32_t kMaxSpins = 1u << 22;
+constexpr uint32_t kEpochBits = (1u << 30) - 1u;
 __device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint64_t flag, uint32_t v)
 {
-    return ((uint64_t)epoch << 34) | (flag << 32) | v;
+    return ((uint64_t)(epoch & kEpochBits) << 34) | (flag << 32) | v;
 }
 
 template <int BLOCK> struct ScanShared {
@@ -88,7 +89,7 @@ __device__ __forceinline__ uint32_t lookback_queue(const uint64_t* status, uint3
         const long long j = hi - lane;
         uint64_t s = pack_status(epoch, kFlagInc, 0);   // before chunk 0: an inclusive zero
         if (j >= 0) s = __hip_atomic_load(status + (size_t)j * 3 + q, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const bool ok = (uint32_t)(s >> 34) == epoch && ((s >> 32) & 3ull) != 0;
+        const bool ok = (uint32_t)(s >> 34) == (epoch & kEpochBits) && ((s >> 32) & 3ull) != 0;
         const bool inc = ok && ((s >> 32) & 3ull) == kFlagInc;
         const uint64_t inc_mask = __ballot(inc);
         const uint64_t bad_mask = __ballot(!ok);

@@ -174,6 +174,7 @@ struct Lib {
     DBuf<gv_trace_rec> trace;
     DBuf<unsigned long long> esc_hist;
     DBuf<unsigned long long> trace_n;
+    DBuf<unsigned long long> snap;   // counters, escape histogram, trace count before a window
     DBuf<PrimDev> prim;
     DBuf<uint32_t> prim_slot;
     Ctrl* h_ctrl = nullptr;  // pinned
@@ -188,6 +189,7 @@ struct Lib {
     int64_t last_events = 0;
     double init_ms = 0.0;
     double plain_loads = 0.0, plain_stores = 0.0;
+    int64_t tail_steps0 = 0;   // step counter when the current window entered its tail
     bool progress = std::getenv("GV_PROGRESS") != nullptr;   // print the population per graph replay
     // the staged batch (gv_stage): primaries grouped by event, resident on the device
     std::vector<PrimDev> hp;
@@ -284,6 +286,7 @@ void release_all()
     L.trace.release();
     L.esc_hist.release();
     L.trace_n.release();
+    L.snap.release();
     L.prim.release();
     L.prim_slot.release();
     if (L.h_ctrl) (void)hipHostFree(L.h_ctrl);
@@ -526,6 +529,7 @@ int ensure_common(int64_t n_events)
         drop_graph();
         HIPCHK(L.esc_hist.ensure(kEhSize));
     }
+    HIPCHK(L.snap.ensure(kNCount + kEhSize + 1));
     if (!L.h_ctrl) HIPCHK(hipHostMalloc((void**)&L.h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     if (!L.ev0) HIPCHK(hipEventCreate(&L.ev0));
     if (!L.ev1) HIPCHK(hipEventCreate(&L.ev1));
@@ -567,6 +571,45 @@ Sinks make_sinks()
     return S;
 }
 
+// Launches one event window may take before the driver reports a stuck loop.
+// Every launch moves every live track by at least one step and a track ends
+// within max_steps_per_track + 1 launches, but each secondary starts again at
+// step 0, so the bound allows a tree of secondaries kMaxGenerations deep (no
+// electromagnetic shower of these energies comes near it); it is also capped
+// so that the look-back epoch cannot wrap inside a window.
+constexpr uint32_t kEpochMask = (1u << 30) - 1u;
+constexpr int64_t kMaxWindowLaunches = (int64_t)1 << 26;
+constexpr int64_t kMaxGenerations = 256;
+int64_t window_launch_bound()
+{
+    return std::min<int64_t>((L.cfg.max_steps_per_track + 2) * kMaxGenerations, kMaxWindowLaunches);
+}
+
+// Device accumulators that a window adds to besides its own deposit and
+// ledger rows: kept before each window and put back when the window is
+// rerun with fewer events in flight, so a retried window counts once.
+int snapshot_sinks()
+{
+    hipStream_t s = stream();
+    HIPCHK(hipMemcpyAsync(L.snap.p, L.counters.p, kNCount * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L.snap.p + kNCount, L.esc_hist.p, kEhSize * sizeof(unsigned long long),
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L.snap.p + kNCount + kEhSize, L.trace_n.p, sizeof(unsigned long long),
+                          hipMemcpyDeviceToDevice, s));
+    return GV_OK;
+}
+
+int restore_sinks()
+{
+    hipStream_t s = stream();
+    HIPCHK(hipMemcpyAsync(L.counters.p, L.snap.p, kNCount * sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L.esc_hist.p, L.snap.p + kNCount, kEhSize * sizeof(unsigned long long),
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(L.trace_n.p, L.snap.p + kNCount + kEhSize, sizeof(unsigned long long),
+                          hipMemcpyDeviceToDevice, s));
+    return GV_OK;
+}
+
 // set the control block for a window: input counts at parity 0
 int upload_ctrl(const uint32_t counts[3], uint64_t seed)
 {
@@ -584,7 +627,12 @@ int upload_ctrl(const uint32_t counts[3], uint64_t seed)
     c.done = 0;
     c.halt = 0;
     c.seed = seed;
-    if (c.epoch == 0) c.epoch = 1;
+    if (c.epoch == 0 || c.epoch > kEpochMask - kMaxWindowLaunches) {
+        // status words hold 30 bits of the epoch: restart it at 1 over zeroed
+        // words before a window could carry it past the mask
+        HIPCHK(hipMemsetAsync(L.status.p, 0, L.status.n * sizeof(uint64_t), s));
+        c.epoch = 1;
+    }
     *L.h_ctrl = c;
     HIPCHK(hipMemcpyAsync(L.ctrl.p, L.h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -712,6 +760,7 @@ template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
 template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, const Tuning& tu)
 {
     QueueMem<P>& Q = batch_queues<P>();
+    L.tail_steps0 = 0;
     uint32_t counts[3];
     int rc = ingest<P>(b, e, Q.q[0], counts, Q.cap, false);
     if (rc) return rc;
@@ -743,10 +792,21 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     hipStream_t s = stream();
     uint32_t population = counts[0] + counts[1] + counts[2];
     uint32_t peak = population;
+    int64_t launches = 0;
+    const int64_t bound = window_launch_bound();
+    bool in_tail = false;
     for (;;) {
         // once the population has passed its peak and fallen below the tail
         // threshold, replay the tail graph (more launches per replay)
         const bool tail = population < tu.tail && peak >= tu.tail;
+        if (tail && !in_tail) {
+            // the steps taken so far, so that the tail's own steps can be told apart
+            unsigned long long c3[3];
+            HIPCHK(hipMemcpyAsync(c3, L.counters.p + kCSteps, sizeof(c3), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            L.tail_steps0 += (int64_t)(c3[0] + c3[1] + c3[2]);
+            in_tail = true;
+        }
         HIPCHK(hipEventRecord(L.ev0, s));
         HIPCHK(hipGraphLaunch(tail ? L.gexec_tail : L.gexec, s));
         HIPCHK(hipEventRecord(L.ev1, s));
@@ -760,6 +820,7 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
         L.stats.kernel_launches += K;
         L.stats.iterations += K;
         L.stats.graph_replays += 1;
+        launches += K;
         if (L.h_ctrl->overflow & 2u) return fail(GV_E_STATE, "compaction look-back wait exceeded its bound");
         if (L.h_ctrl->overflow) return GV_E_CAPACITY;
         const uint32_t* c = L.h_ctrl->count[0];
@@ -768,11 +829,17 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
                          (long long)L.stats.graph_replays, tail ? "tail" : "bulk", ms, c[0], c[1], c[2]);
         population = c[0] + c[1] + c[2];
         peak = std::max(peak, population);
-        if (population == 0) break;
-        // every launch advances each live track by at least one step, so the
-        // looper cap bounds the number of launches
-        if (L.stats.iterations > 2 * L.cfg.max_steps_per_track + 64)
-            return fail(GV_E_STATE, "step loop did not terminate within the looper cap");
+        if (population == 0) {
+            if (in_tail) {
+                unsigned long long c3[3];
+                HIPCHK(hipMemcpyAsync(c3, L.counters.p + kCSteps, sizeof(c3), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                L.stats.tail_steps += (int64_t)(c3[0] + c3[1] + c3[2]) - L.tail_steps0;
+                L.tail_steps0 = 0;
+            }
+            break;
+        }
+        if (launches > bound) return fail(GV_E_STATE, "step loop did not terminate within its launch bound");
     }
     return GV_OK;
 }
@@ -793,6 +860,8 @@ int run_plain_window(size_t b, size_t e, uint64_t seed)
     uint32_t n = counts[0];
     int parity = 0;
     const int TB = 256;
+    int64_t launches = 0;
+    const int64_t bound = window_launch_bound();
     while (n > 0) {
         PlainArgs A;
         A.pool = Q.q[parity][0];
@@ -833,8 +902,7 @@ int run_plain_window(size_t b, size_t e, uint64_t seed)
         parity ^= 1;
         n = L.h_ctrl->count[parity][0];
         L.plain_stores += n;
-        if (L.stats.iterations > 2 * L.cfg.max_steps_per_track + 64)
-            return fail(GV_E_STATE, "step loop did not terminate within the looper cap");
+        if (++launches > bound) return fail(GV_E_STATE, "step loop did not terminate within its launch bound");
     }
     return GV_OK;
 }
@@ -932,7 +1000,8 @@ template <class P> int tuned_choice(int64_t n_events, uint64_t seed, std::array<
     double best_rate = 0.0;
     int rc = trial(best, best_rate);
     if (rc) return rc;
-    static const int kCand[3][6] = {{64, 128, 256, 512, 0, 0}, {1, 2, 3, 4, 6, 8}, {1, 2, 4, 8, 0, 0}};
+    static const int kCand[3][8] = {{64, 128, 256, 512, 1024, 2048, 4096, 0}, {1, 2, 3, 4, 6, 8, 0, 0},
+                                    {1, 2, 4, 8, 0, 0, 0, 0}};
     const int fixed[3] = {L.cfg.basket, L.cfg.occupancy, L.cfg.inner_steps};
     for (int knob : {2, 0, 1}) {
         if (fixed[knob]) continue;
@@ -994,13 +1063,18 @@ template <class P> int transport_batched(int64_t n_events, uint64_t seed)
     int64_t e0 = 0;
     while (e0 < n_events) {
         const int64_t e1 = std::min(n_events, e0 + window);
+        rc = snapshot_sinks();
+        if (rc) return rc;
         rc = run_batched_window<P>(ev_start[e0], ev_start[e1], seed, tu);
         if (rc == GV_E_CAPACITY) {
             if (e1 - e0 <= 1) return fail(GV_E_CAPACITY, "track queues overflow with one event in flight");
-            // undo the window's partial deposits and retry with half the events
+            // undo the window's partial deposits, ledger rows and counters and
+            // retry with half the events
             const size_t nc = (size_t)std::max(L.n_cells, 1);
             HIPCHK(hipMemsetAsync(L.edep.p + (size_t)e0 * nc, 0, (size_t)(e1 - e0) * nc * sizeof(double), stream()));
             HIPCHK(hipMemsetAsync(L.ledger.p + (size_t)e0 * 4, 0, (size_t)(e1 - e0) * 4 * sizeof(double), stream()));
+            rc = restore_sinks();
+            if (rc) return rc;
             window = std::max<int64_t>(1, (e1 - e0) / 2);
             L.stats.overflow_restarts += 1;
             continue;
@@ -1024,12 +1098,19 @@ int transport_plain(int64_t n_events, uint64_t seed)
     int64_t e0 = 0;
     while (e0 < n_events) {
         const int64_t e1 = std::min(n_events, e0 + window);
+        rc = snapshot_sinks();
+        if (rc) return rc;
+        const double loads0 = L.plain_loads, stores0 = L.plain_stores;
         rc = run_plain_window(ev_start[e0], ev_start[e1], seed);
         if (rc == GV_E_CAPACITY) {
             if (e1 - e0 <= 1) return fail(GV_E_CAPACITY, "track pool overflow with one event in flight");
             const size_t nc = (size_t)std::max(L.n_cells, 1);
             HIPCHK(hipMemsetAsync(L.edep.p + (size_t)e0 * nc, 0, (size_t)(e1 - e0) * nc * sizeof(double), stream()));
             HIPCHK(hipMemsetAsync(L.ledger.p + (size_t)e0 * 4, 0, (size_t)(e1 - e0) * 4 * sizeof(double), stream()));
+            rc = restore_sinks();
+            if (rc) return rc;
+            L.plain_loads = loads0;
+            L.plain_stores = stores0;
             window = std::max<int64_t>(1, (e1 - e0) / 2);
             L.stats.overflow_restarts += 1;
             continue;

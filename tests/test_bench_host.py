@@ -56,3 +56,12 @@ def test_measured_traffic_matches_source_workload_and_knobs(tmp_path, monkeypatc
 def test_source_hash_covers_the_kernel_sources():
     h = bench.kernel_source_hash()
     assert len(h) == 40 and h == bench.kernel_source_hash()
+
+
+def test_host_cpus_and_ungated_comparison():
+    c = bench.host_cpus()
+    assert 1 <= c["threads"] <= 16 and c["threads"] <= c["available"]
+    rng = np.random.default_rng(5)
+    y = rng.gamma(4.0, 1.0, size=(200, 10))
+    r = bench.paired_layers(y + rng.normal(0, 0.5, y.shape), y, gate=False)
+    assert "pass_" not in r and r["three_sigma_rel_median_big_layers"] > 0 and r["events"] == 200

@@ -64,6 +64,12 @@ CASES = {
     "field_e100": (lambda: gv_inputs.slab_calorimeter(10, (0.0, 4.0, 0.0)), lambda: gv_inputs.beam(10, 11, 100.0)),
     "barrel_g50": (lambda: gv_inputs.barrel(), lambda: gv_inputs.barrel_beam(4, 5, 50.0)),
 }
+# History tolerance per case, normwise: without a field the GPU and the oracle
+# round the same expressions in the same order (measured worst 9e-13); in a
+# field, helix phases carry last-bit differences of the trigonometric
+# functions and amplify them along hundreds of steps (measured 1e-10 on the
+# slab in 4 T, 3.3e-8 in the barrel with table sampling).
+HIST_TOL = {"slab_e10": 1e-11, "slab_g50": 1e-11, "field_e100": 1e-8, "barrel_g50": 1e-7}
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -85,16 +91,15 @@ def test_tiny_shower_histories_fp64(gv, oracle_mod, case, driver):
     got = eng.trace()
     st = eng.stats()
     assert st["trace_records"] < 2_000_000
-    missing, extra, bad, worst = _compare_histories(got, ref["trace"], 1e-6)
+    missing, extra, bad, worst = _compare_histories(got, ref["trace"], HIST_TOL[case])
     n_ref = len(ref["trace"])
     print(f"\n[{case}/{driver}] oracle steps {n_ref}, gpu {len(got)}, missing {missing}, extra {extra}, "
           f"discrete mismatches {bad}, worst scaled error {worst:.2e}")
-    assert missing <= n_ref * 1e-3 and extra <= n_ref * 1e-3 and bad <= max(2, n_ref * 1e-3)
+    assert missing == 0 and extra == 0 and bad == 0
     # single steps agree to 1e-12; along a history the differences are carried
     # and amplified by later steps (scattering angles, helix phases, distances
-    # to nearly tangent boundaries): hundreds of field steps of one electron in
-    # the barrel take 1e-16 to ~3e-8
-    assert worst < 1e-6
+    # to nearly tangent boundaries)
+    assert worst < HIST_TOL[case]
     assert np.allclose(edep, ref["edep"], rtol=1e-8, atol=1e-8 * max(1.0, ref["edep"].max()))
     counts = ref["counters"]
     assert st["total_steps"] == counts["steps_gamma"] + counts["steps_electron"] + counts["steps_positron"] \
@@ -185,13 +190,23 @@ def test_capacity_overflow_restarts(gv, mode):
         cfg["driver"] = gv.DRIVER_PLAIN
     else:
         cfg["queue_order"] = gv.ORDER_ARRIVAL if mode == "arrival" else gv.ORDER_STABLE
-    ref = gv.Engine(geom, **cfg).transport(prim, seed)
+    cfg["trace_cap"] = 1_000_000
+    eng0 = gv.Engine(geom, **cfg)
+    ref = eng0.transport(prim, seed)
+    st0, h0 = eng0.stats(), eng0.escape_hist()
+    eng0.close()
     eng = gv.Engine(geom, capacity=256, **cfg)
     e = eng.transport(prim, seed)
     st = eng.stats()
     print(f"\n[overflow {mode}] restarts {st['overflow_restarts']}")
     assert st["overflow_restarts"] > 0
     assert np.allclose(e, ref, rtol=1e-12, atol=1e-12 * max(1.0, ref.max()))
+    # counters, escape spectra and step records of the discarded windows are
+    # taken back: the totals equal those of the run with ample capacity
+    for k in ("steps", "tracks", "interactions", "escaped", "killed", "trace_records", "rejection_exhausted"):
+        assert st[k] == st0[k], (k, st[k], st0[k])
+    assert np.array_equal(eng.escape_hist(), h0)
+    assert st["state_bytes"] <= st0["state_bytes"] * 1.5 + 1e6
 
 
 @pytest.mark.parametrize("fs", ["rejection", "tables", "field_c3"])
