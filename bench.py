@@ -351,8 +351,9 @@ def run_field_map(args, gv, torch, cfg):
     edep = torch.zeros((int(prim["event"].max()) + 1, eng.n_cells), dtype=torch.float64, device="cuda:0")
     eng.stage(prim)
     out = dict(workload=f"c5m: {len(prim)} x 50 GeV e-/gamma, barrel in a 3.8 T finite solenoid")
-    for name, fm in (("helix", gv.FIELD_HELIX), ("rk45", gv.FIELD_RK45)):
-        eng.configure(field_method=fm)
+    for name, fm, order in (("helix", gv.FIELD_HELIX, gv.ORDER_ARRIVAL), ("rk45", gv.FIELD_RK45, gv.ORDER_ARRIVAL),
+                            ("rk45_in_step", gv.FIELD_RK45, gv.ORDER_STABLE)):
+        eng.configure(field_method=fm, queue_order=order)
         eng.transport_staged(seed, edep.data_ptr())
         ts, steps, sub, rej, slots, charged, kms = [], 0, 0, 0, 0, 0, 0.0
         reps = 3 if fm == gv.FIELD_HELIX else 2
@@ -372,13 +373,18 @@ def run_field_map(args, gv, torch, cfg):
         leg = dict(steps_per_s=steps / sum(ts), ms_per_transport=float(np.median(ts)) * 1e3,
                    kernel_ms_per_transport=kms / reps, e_dep_GeV=float(st["e_dep"]) * 1e-3 / len(prim),
                    tail_kernel_ms=float(st["tail_kernel_ms"]))
+        if name == "rk45":
+            leg["integration"] = ("integration queue: charged steps parked at their RK45 move while the population "
+                                  "fills the GPU, integrated by one kernel with lanes refilled at every attempt")
+        if name == "rk45_in_step":
+            leg["integration"] = "each lane integrates its own track inside the step (stable-order queues)"
         if fm == gv.FIELD_RK45:
             leg.update(substeps_per_charged_step=sub / max(charged, 1), rejected_per_charged_step=rej / max(charged, 1),
                        substeps_per_s=sub / sum(ts), idle_lane_fraction=1.0 - (sub + rej) / max(slots, 1))
         out[name] = leg
         log(f"[bench] field map {name}: {leg['steps_per_s']:.3g} steps/s, {leg['ms_per_transport']:.1f} ms"
             + (f", {leg['substeps_per_charged_step']:.2f} substeps + {leg['rejected_per_charged_step']:.2f} "
-               f"rejected per charged step, idle lanes {leg['idle_lane_fraction']:.3f}" if name == "rk45" else ""))
+               f"rejected per charged step, idle lanes {leg['idle_lane_fraction']:.3f}" if fm == gv.FIELD_RK45 else ""))
     eng.close()
     return out
 
@@ -483,8 +489,8 @@ def copy_probe(nbytes, reps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--basket", type=int, default=0)

@@ -227,15 +227,18 @@ typedef struct {
                                        fell below the tail threshold (batched driver) */
     int64_t rk_substeps;            /* RK45: accepted substeps */
     int64_t rk_rejected;            /* RK45: rejected attempts */
-    int64_t rk_lane_slots;          /* RK45: for every group of lanes of one wavefront that
-                                       integrate together, (lanes) x (most attempts among
-                                       them); 1 - (substeps + rejected) / lane_slots is the
-                                       fraction of idle lanes in the integration loop */
+    int64_t rk_lane_slots;          /* RK45: 64 x the attempt rounds of every wavefront that
+                                       integrates (inside a step: as many rounds as its lane
+                                       with the most attempts; in the integration queue: every
+                                       round while any of its lanes holds an integration);
+                                       1 - (substeps + rejected) / lane_slots is the fraction
+                                       of idle lanes in the integration loop */
     int64_t lane_slots;             /* batched driver: 64 x (step-loop iterations) summed over the
                                        wavefronts of every basket, a wavefront running as many
                                        iterations as its busiest lane; total steps / lane_slots is
                                        the lane use of the stepping loop (0 for the plain driver) */
     int64_t tail_steps;             /* steps taken in the launches counted in tail_kernel_ms */
+    int64_t helper_steps;           /* of those, steps taken by the tail's vacuum helper kernel */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

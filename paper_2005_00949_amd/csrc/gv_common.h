@@ -25,8 +25,9 @@ enum : int { kCompton = 0, kPair = 1, kMoller = 2, kBhabha = 3, kBremsEm = 4, kB
 // random-stream purposes: low 8 bits of the fourth counter word
 enum : uint32_t { kPurpStep = 0, kPurpMsc = 1, kPurpChild = 2, kPurpAnnih = 3, kPurpFs0 = 16,
                   kFsMaxIter = 240 };
-// track status after a step
-enum : int { kAlive = 0, kDead = 1, kEscaped = 2, kKilled = 3 };
+// track status after a step (kParked: stopped at its RK45 move, waiting in
+// the batched driver's integration queue)
+enum : int { kAlive = 0, kDead = 1, kEscaped = 2, kKilled = 3, kParked = 4 };
 // per-material table record columns (4 per node and particle type)
 //   gamma: Sigma_compton, Sigma_pair, -, -
 //   e-   : Sigma_moller, Sigma_brems, S (restricted dE/dx), R (range)

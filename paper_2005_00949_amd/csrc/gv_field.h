@@ -146,11 +146,135 @@ constexpr double kDpK = 8.1e-4;
 // substep length an exact function of s and theta.  After max_sub attempts
 // the integration stops.  Stage sums run in stage order as fused
 // multiply-adds (zero coefficients skipped), as does the stage point
-// y + h sum.  Returns the length integrated (s unless attempts ran out).
+// y + h sum.
 //
-// The loop runs while any lane of the wavefront still integrates, each lane
-// working only while it has work: every lane then knows how many iterations
-// its wavefront spent, which gives the idle-lane statistic at no extra cost.
+// The integration is written as a state and one attempt at a time, so that
+// a lane can run one track's attempts inside its own loop (rk45_move) or
+// take attempts of whichever integration it holds from a shared queue (the
+// batched driver's integration kernel): both run the same arithmetic.  The
+// first stage derivative of an attempt is the direction itself (dx/ds = u),
+// and first-same-as-last carries the Lorentz term ku0 of the accepted end
+// point into the next attempt.
+struct Rk45State {
+    double x[3], u[3], ku0[3];
+    double done, h, s, kq;
+    int acc, rej;
+    bool busy;
+};
+
+__device__ inline void rk45_begin(const DevGeom& g, int type, double T, double s, double tol, const double pos[3],
+                                  const double u[3], Rk45State& st)
+{
+#pragma clang fp contract(off)
+    st.acc = 0;
+    st.rej = 0;
+    st.done = 0.0;
+    st.s = s;
+    st.busy = s > 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st.x[a] = pos[a];
+        st.u[a] = u[a];
+    }
+    if (!st.busy) return;
+    const double q = type == kElectron ? -1.0 : 1.0;
+    const double p = sqrt(T * (T + 2.0 * kMe));
+    st.kq = q * kKB / p;
+    {
+        double B[3];
+        field_at<double>(g, st.x, B);
+        lorentz<double>(st.kq, B, st.u, st.ku0);
+    }
+    st.h = s;
+    {
+        const double w = sqrt(st.ku0[0] * st.ku0[0] + st.ku0[1] * st.ku0[1] + st.ku0[2] * st.ku0[2]);
+        const double theta = 0.8 * sqrt(sqrt(tol / kDpK));
+        if (st.h * w > theta) st.h = theta / w;
+    }
+}
+
+// one attempt of a busy integration; clears busy when it is done
+__device__ inline void rk45_attempt(const DevGeom& g, double tol, int max_sub, Rk45State& st)
+{
+#pragma clang fp contract(off)
+    double kx[7][3], ku[7][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        kx[0][a] = st.u[a];
+        ku[0][a] = st.ku0[a];
+    }
+    const double rem = st.s - st.done;
+    const bool last = st.h >= rem;
+    double h = last ? rem : st.h;
+    double xs[3], us[3];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double sx = kDpA[i][0] * kx[0][a];
+            double su = kDpA[i][0] * ku[0][a];
+#pragma unroll
+            for (int j = 1; j < i; ++j) {
+                if (kDpA[i][j] != 0.0) {
+                    sx = fma(kDpA[i][j], kx[j][a], sx);
+                    su = fma(kDpA[i][j], ku[j][a], su);
+                }
+            }
+            xs[a] = fma(h, sx, st.x[a]);
+            us[a] = fma(h, su, st.u[a]);
+        }
+        double B[3];
+        field_at<double>(g, xs, B);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) kx[i][a] = us[a];
+        lorentz<double>(st.kq, B, us, ku[i]);
+    }
+    // xs, us: the 5th-order solution (the last stage point)
+    double err = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double ex = kDpE[0] * kx[0][a];
+#pragma unroll
+        for (int j = 2; j < 7; ++j) ex = fma(kDpE[j], kx[j][a], ex);
+        if (fabs(ex) > err) err = fabs(ex);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double eu = kDpE[0] * ku[0][a];
+#pragma unroll
+        for (int j = 2; j < 7; ++j) eu = fma(kDpE[j], ku[j][a], eu);
+        eu = h * eu;
+        if (fabs(eu) > err) err = fabs(eu);
+    }
+    if (err <= tol) {
+        st.acc += 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            st.x[a] = xs[a];
+            st.u[a] = us[a];
+            st.ku0[a] = ku[6][a];
+        }
+        if (last) {
+            st.done = st.s;
+            st.h = h;
+            st.busy = false;
+        } else {
+            st.done += h;
+            st.h = h;
+            if (err <= tol * (1.0 / 16.0)) st.h *= 2.0;
+        }
+    } else {
+        st.rej += 1;
+        st.h = h * 0.5;
+    }
+    if (st.acc + st.rej >= max_sub) st.busy = false;
+}
+
+// One track's whole integration on its own lane.  The loop runs while any
+// lane of the wavefront still integrates, each lane working only while it has
+// work: every lane then knows how many iterations its wavefront spent, which
+// gives the idle-lane statistic.  Returns the length integrated (s unless
+// attempts ran out); pos and u (normalised) are updated.
 __device__ inline double rk45_move(const DevGeom& g, int type, double T, double s, double tol, int max_sub,
                                    double pos[3], double u[3], RkTally& tally)
 {
@@ -159,95 +283,21 @@ __device__ inline double rk45_move(const DevGeom& g, int type, double T, double 
     tally.rej = 0;
     tally.iters = 0;
     if (!(s > 0.0)) return 0.0;
-    const double q = type == kElectron ? -1.0 : 1.0;
-    const double p = sqrt(T * (T + 2.0 * kMe));
-    const double kq = q * kKB / p;
-    // stage derivatives: kx[j] = direction at stage j, ku[j] = its Lorentz term
-    double kx[7][3], ku[7][3];
-    {
-        double B[3];
-        field_at<double>(g, pos, B);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) kx[0][a] = u[a];
-        lorentz<double>(kq, B, u, ku[0]);
-    }
-    double done = 0.0, h = s;
-    {
-        const double w = sqrt(ku[0][0] * ku[0][0] + ku[0][1] * ku[0][1] + ku[0][2] * ku[0][2]);
-        const double theta = 0.8 * sqrt(sqrt(tol / kDpK));
-        if (h * w > theta) h = theta / w;
-    }
-    bool busy = true;
-    while (__any(busy)) {
+    Rk45State st;
+    rk45_begin(g, type, T, s, tol, pos, u, st);
+    while (__any(st.busy)) {
         tally.iters += 1;
-        if (!busy) continue;
-        const double rem = s - done;
-        const bool last = h >= rem;
-        if (last) h = rem;
-        double xs[3], us[3];
+        if (st.busy) rk45_attempt(g, tol, max_sub, st);
+    }
+    tally.acc = st.acc;
+    tally.rej = st.rej;
 #pragma unroll
-        for (int i = 1; i < 7; ++i) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double sx = kDpA[i][0] * kx[0][a];
-                double su = kDpA[i][0] * ku[0][a];
-#pragma unroll
-                for (int j = 1; j < i; ++j) {
-                    if (kDpA[i][j] != 0.0) {
-                        sx = fma(kDpA[i][j], kx[j][a], sx);
-                        su = fma(kDpA[i][j], ku[j][a], su);
-                    }
-                }
-                xs[a] = fma(h, sx, pos[a]);
-                us[a] = fma(h, su, u[a]);
-            }
-            double B[3];
-            field_at<double>(g, xs, B);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) kx[i][a] = us[a];
-            lorentz<double>(kq, B, us, ku[i]);
-        }
-        // xs, us: the 5th-order solution (the last stage point)
-        double err = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double ex = kDpE[0] * kx[0][a];
-#pragma unroll
-            for (int j = 2; j < 7; ++j) ex = fma(kDpE[j], kx[j][a], ex);
-            if (fabs(ex) > err) err = fabs(ex);
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double eu = kDpE[0] * ku[0][a];
-#pragma unroll
-            for (int j = 2; j < 7; ++j) eu = fma(kDpE[j], ku[j][a], eu);
-            eu = h * eu;
-            if (fabs(eu) > err) err = fabs(eu);
-        }
-        if (err <= tol) {
-            tally.acc += 1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                pos[a] = xs[a];
-                u[a] = us[a];
-                kx[0][a] = kx[6][a];
-                ku[0][a] = ku[6][a];
-            }
-            if (last) {
-                done = s;
-                busy = false;
-            } else {
-                done += h;
-                if (err <= tol * (1.0 / 16.0)) h *= 2.0;
-            }
-        } else {
-            tally.rej += 1;
-            h *= 0.5;
-        }
-        if (tally.acc + tally.rej >= max_sub) busy = false;
+    for (int a = 0; a < 3; ++a) {
+        pos[a] = st.x[a];
+        u[a] = st.u[a];
     }
     normalise(u);
-    return done;
+    return st.done;
 }
 
 }  // namespace gv

@@ -84,7 +84,8 @@ __device__ __forceinline__ void store_child(const Soa<P>& q, size_t i, const Tra
 
 // global counters (gv_stats)
 enum : int { kCSteps = 0, kCTracks = 3, kCProc = 6, kCEscaped = 14, kCKilled = 15, kCRej = 16, kCLoads = 17,
-             kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kCLaneSlots = 22, kNCount = 23 };
+             kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kCLaneSlots = 22, kCHelperSteps = 23,
+             kNCount = 24 };
 
 // per-lane sums of the adaptive-integration tallies over one launch
 struct RkSum {
@@ -617,6 +618,26 @@ struct Ctrl {
     uint32_t halt;          // overflow as seen at the end of the previous launch
     uint32_t pad;
     uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
+    uint32_t rk_count[2];   // integration queue: moves parked in this launch, per charged type
+    uint32_t rk_grab;       // next parked move for the integration kernel
+    uint32_t rk_ticket;     // next chunk of parked moves for the resume kernel
+    uint32_t rk_done;       // resume workgroups finished in this launch
+    uint32_t pad2;
+};
+
+// A step parked at its RK45 move (the integration queue of the batched
+// driver): the track before the move, what the rest of the step needs, and
+// the integration's result once the integration kernel has run it.
+template <class P> struct RkJob {
+    using R = typename P::R;
+    Track<P> t;
+    Limits<R> L;
+    Geo G;
+    double s;          // length to integrate
+    int lim;           // nominal limiter of the step
+    int acc, rej;      // accepted and rejected attempts
+    double s_done;     // length integrated
+    double x[3], u[3]; // end point and unit direction
 };
 
 template <class P> struct BatchArgs {
@@ -632,6 +653,8 @@ template <class P> struct BatchArgs {
     uint32_t tail_threshold; // population below which the tail setting applies
     Sinks S;
     TabView<typename P::R> tv;
+    RkJob<P>* jobs[2];       // integration queue per charged type (RK45 with arrival order)
+    uint32_t jcap;           // its capacity per type
 };
 
 // Primary ingest (the event server of Sec. 2.1): validated, typed primaries
@@ -712,12 +735,37 @@ __device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[
 // photon and charged-particle step paths are specialised): step each track up
 // to `inner` times in registers, stopping at its first secondary or its end;
 // then compact survivor + secondaries into the output queues.
-template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, class R = typename P::R>
+// Park one step at its RK45 move in the integration queue (lanes parking in
+// the same iteration reserve their slots with one atomic per wavefront).
+template <class P, int TY, class R = typename P::R>
+__device__ __forceinline__ void park_job(const BatchArgs<P>& A, const Track<P>& t, const Limits<R>& L, const Geo& G,
+                                         const Prop<R>& pr)
+{
+    const uint64_t pm = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)pm) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&A.ctrl->rk_count[TY - 1], (uint32_t)__popcll(pm));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    const uint32_t k = base + (uint32_t)__popcll(pm & ((1ull << lane) - 1ull));
+    if (k < A.jcap) {
+        RkJob<P>& J = A.jobs[TY - 1][k];
+        J.t = t;
+        J.L = L;
+        J.G = G;
+        J.s = pr.s;
+        J.lim = pr.lim;
+    } else {
+        atomicOr(&A.ctrl->overflow, 1u);
+    }
+}
+
+template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, bool PARK = false, class R = typename P::R>
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
                                               uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks,
-                                              unsigned long long* lane_slots_lds, bool vac_ok)
+                                              unsigned long long* lane_slots_lds, bool vac_ok, bool park)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -748,8 +796,9 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                 // matter), so such steps repeat with only the step count and
                 // the trace; the step that ends otherwise takes the
                 // bookkeeping below like any other.
+                const WorldRun<P> run = world_run(c, t);
                 for (;;) {
-                    step_track<P, false, true, true>(c, t, o);
+                    step_world(c, run, t, o);
                     steps_here += o.did_step;
                     iters += 1;
                     if (o.status != kAlive || t.vol != 0 || iters >= inner) break;
@@ -767,6 +816,17 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                     if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
                     ns = t.nstep;
                 }
+            } else if (PARK && TY != kGamma && park) {
+                Limits<R> L;
+                Geo G;
+                Prop<R> pr;
+                iters += 1;
+                if (step_track_park(c, t, o, L, G, pr)) {
+                    park_job<P, TY>(A, t, L, G, pr);
+                    o.status = kParked;
+                    break;
+                }
+                steps_here += o.did_step;
             } else {
                 step_track<P, INTEG>(c, t, o);
                 steps_here += o.did_step;
@@ -850,7 +910,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
 // variant leaves them out and keeps its register budget.  The mixed-precision
 // helix variant is held to three wavefronts per SIMD (168 VGPRs): the step
 // chain is latency-bound, and a third resident wavefront hides more of it.
-template <class P, int BLOCK, bool STABLE, bool INTEG>
+template <class P, int BLOCK, bool STABLE, bool INTEG, bool PARK = false>
 __global__ void __launch_bounds__(BLOCK, (!INTEG && sizeof(typename P::R) == sizeof(float)) ? 3 : 1)
 k_step_batched(BatchArgs<P> A)
 {
@@ -876,6 +936,10 @@ k_step_batched(BatchArgs<P> A)
     const uint32_t n_chunks = c0 + c1 + c2;
     const uint32_t population = n0 + n1 + n2;
     const int inner = population < A.tail_threshold ? A.inner_tail : A.inner_bulk;
+    // the integration queue pays off while the population fills the GPU; in
+    // the low-population tail each lane integrates its own track (inner_tail
+    // steps per launch instead of one parked step per launch)
+    const bool park = PARK && population >= A.tail_threshold;
     // only as many workgroups as there are baskets take part; the rest leave
     // at once, so a small population costs a small launch
     const uint32_t baskets = (n_chunks + (uint32_t)A.basket_chunks - 1) / (uint32_t)A.basket_chunks;
@@ -897,14 +961,17 @@ k_step_batched(BatchArgs<P> A)
         const uint32_t last = min(first + (uint32_t)A.basket_chunks, n_chunks);
         for (uint32_t chunk = first; chunk < last; ++chunk) {
             if (chunk < c0)
-                process_chunk<P, kGamma, BLOCK, STABLE, INTEG>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc, cnt_lds, steps_g,
-                                                loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
+                process_chunk<P, kGamma, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc,
+                                                                     cnt_lds, steps_g, loads, stores, n_chunks, rks,
+                                                                     &rk_lds[3], vac_ok, park);
             else if (chunk < c0 + c1)
-                process_chunk<P, kElectron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner, sh, dc, cnt_lds,
-                                                   steps_e, loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
+                process_chunk<P, kElectron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner,
+                                                                        sh, dc, cnt_lds, steps_e, loads, stores, n_chunks,
+                                                                        rks, &rk_lds[3], vac_ok, park);
             else
-                process_chunk<P, kPositron, BLOCK, STABLE, INTEG>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch, inner, sh, dc,
-                                                   cnt_lds, steps_p, loads, stores, n_chunks, rks, &rk_lds[3], vac_ok);
+                process_chunk<P, kPositron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch,
+                                                                        inner, sh, dc, cnt_lds, steps_p, loads, stores,
+                                                                        n_chunks, rks, &rk_lds[3], vac_ok, park);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);
@@ -959,11 +1026,13 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
     int calls = 0, kept = 0;
     if (active) {
+        // vacuum keeps the kinetic energy: the run constants hold for every kept step
+        const WorldRun<P> run = world_run(c, t);
         for (; calls < max_steps;) {
             Track<P> tn = t;
             StepOut<R> o;
             const uint32_t ns = t.nstep;
-            if (t.vol == 0) step_track<P, false, true, true>(c, tn, o);
+            if (t.vol == 0) step_world(c, run, tn, o);
             else step_track<P, false, true>(c, tn, o);
             calls += 1;
             if (o.status != kAlive) break;
@@ -975,6 +1044,7 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
         if (kept) {
             store_track(A.in[ty], slot, t);
             atomicAdd(&A.S.counters[kCSteps + ty], (unsigned long long)kept);
+            atomicAdd(&A.S.counters[kCHelperSteps], (unsigned long long)kept);
         }
     }
     // lane slots: the wavefront ran as many step calls as its busiest lane
@@ -982,6 +1052,223 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(&A.S.counters[kCLaneSlots], 64ull * (unsigned)m);
+}
+
+// ===========================================================================
+// Integration queue of the batched driver (RK45 with arrival-order queues):
+// the step kernel parks every charged step at its RK45 move; one kernel runs
+// all parked integrations, each lane taking the next parked move as soon as
+// its current one is done (lanes are refilled at every attempt, so a
+// wavefront never waits for its slowest integration while the queue still
+// holds work); a resume kernel finishes the parked steps and queues their
+// survivors and secondaries.  Arithmetic is that of the fused step.
+// ===========================================================================
+
+constexpr int kRkBlock = 256;
+
+template <class P>
+__global__ void __launch_bounds__(kRkBlock) k_rk_integrate(BatchArgs<P> A)
+{
+    using R = typename P::R;
+    __shared__ unsigned long long slots_lds;
+    if (threadIdx.x == 0) slots_lds = 0ull;
+    __syncthreads();
+    const bool halt = A.ctrl->halt != 0;
+    const uint32_t ne = halt ? 0u : min(A.ctrl->rk_count[0], A.jcap);
+    const uint32_t np = halt ? 0u : min(A.ctrl->rk_count[1], A.jcap);
+    const uint32_t total = ne + np;
+    const double tol = c_phys.rk_tol;
+    const int max_sub = c_phys.rk_max_sub;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    Rk45State st;
+    st.busy = false;
+    RkJob<P>* job = nullptr;
+    bool has = false, dry = total == 0;
+    uint32_t iters = 0;
+    for (;;) {
+        // refill: lanes without an integration take the next parked moves
+        const uint64_t need = __ballot(!has);
+        if (need && !dry) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&A.ctrl->rk_grab, (uint32_t)__popcll(need));
+            base = (uint32_t)__shfl((int)base, leader, 64);
+            if (base + (uint32_t)__popcll(need) >= total) dry = true;
+            if (!has) {
+                const uint32_t j = base + (uint32_t)__popcll(need & below);
+                if (j < total) {
+                    job = j < ne ? &A.jobs[0][j] : &A.jobs[1][j - ne];
+                    const Track<P>& t = job->t;
+                    const double pos[3] = {t.x[0], t.x[1], t.x[2]};
+                    const double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
+                    rk45_begin(c_geom, t.type, (double)t.T, job->s, tol, pos, ud, st);
+                    has = true;
+                }
+            }
+        }
+        if (!__any(has)) {
+            if (dry) break;
+            continue;
+        }
+        iters += 1;   // an attempt round of the wavefront (some lane holds an integration)
+        if (has && st.busy) rk45_attempt(c_geom, tol, max_sub, st);
+        if (has && !st.busy) {
+            // done: the end point and unit direction, as rk45_move leaves them
+            if (job->s > 0.0) normalise(st.u);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                job->x[a] = st.x[a];
+                job->u[a] = st.u[a];
+            }
+            job->s_done = st.done;
+            job->acc = st.acc;
+            job->rej = st.rej;
+            has = false;
+        }
+    }
+    // lane slots: 64 per attempt round of the wavefront (iters is uniform)
+    if (lane == 0 && iters) atomicAdd(&slots_lds, 64ull * iters);
+    __syncthreads();
+    if (threadIdx.x == 0 && slots_lds) atomicAdd(&A.S.counters[kCRkSlots], slots_lds);
+}
+
+// Finish the parked steps of one chunk (TY known at compile time) and queue
+// survivors and secondaries, as process_chunk does after its step.
+template <class P, int TY, int BLOCK, class R = typename P::R>
+__device__ __forceinline__ void resume_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t base, uint32_t n_t,
+                                             ScanShared<BLOCK>& sh, DepCache& dc, unsigned* cnt_lds,
+                                             uint32_t& steps_here, uint32_t& stores, RkSum& rks)
+{
+    const uint32_t slot = base + threadIdx.x;
+    const bool active = slot < n_t;
+    Track<P> t;
+    StepOut<R> o;
+    o.status = kDead;
+    o.nchild = 0;
+    o.ch[0].type = -1;
+    o.ch[1].type = -1;
+    if (active) {
+        const RkJob<P>& J = A.jobs[TY - 1][slot];
+        t = J.t;
+        t.type = TY;
+        Prop<R> pr;
+        pr.s = J.s;
+        pr.lim = J.lim;
+        const uint32_t ns = t.nstep;
+        const Limits<R> L = J.L;
+        const Geo G = J.G;
+        step_track_resume(c, t, o, L, G, pr, J.x, J.u, J.s_done, J.acc, J.rej);
+        steps_here += o.did_step;
+        rks.acc += (uint32_t)o.rk.acc;
+        rks.rej += (uint32_t)o.rk.rej;
+        DepAcc acc{0.0, 0ull};
+        acc_add(A.S, acc, o.edep);
+        dep_add(dc, A.S, t.ev, o.vol_pre, acc);
+        if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
+        account_rare(A.S, t.ev, o, cnt_lds);
+        if (o.status == kEscaped) escape_count(A.S, TY, t.T, t.u[2]);
+    }
+    dep_flush<BLOCK>(dc, A.S);
+    const int alive = (active && o.status == kAlive) ? 1 : 0;
+    const int q1 = o.nchild > 0 ? o.ch[0].type : -1;
+    const int q2 = o.nchild > 1 ? o.ch[1].type : -1;
+    int cnt[3];
+    cnt[0] = (TY == 0 ? alive : 0) + is_q<0>(q1) + is_q<0>(q2);
+    cnt[1] = (TY == 1 ? alive : 0) + is_q<1>(q1) + is_q<1>(q2);
+    cnt[2] = (TY == 2 ? alive : 0) + is_q<2>(q1) + is_q<2>(q2);
+    int excl[3], tot[3];
+    block_scan3<BLOCK>(cnt, excl, tot, sh);
+    reserve3<BLOCK>(&A.ctrl->count[A.parity ^ 1][0], A.cap, tot, sh, &A.ctrl->overflow);
+    if (alive) {
+        const uint32_t pos = (uint32_t)sh.prefix[TY] + (uint32_t)excl[TY];
+        if (pos < A.cap) {
+            store_track(A.out[TY], pos, t);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    if (q1 >= 0) {
+        const uint32_t pos = (uint32_t)sh.prefix[q1] + (uint32_t)pick3(q1, excl) + (uint32_t)((q1 == TY) & alive);
+        if (pos < A.cap) {
+            store_child_q(A, q1, pos, t, o.ch[0]);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    if (q2 >= 0) {
+        const uint32_t pos = (uint32_t)sh.prefix[q2] + (uint32_t)pick3(q2, excl) +
+                             (uint32_t)((q2 == TY) & alive) + (uint32_t)(q2 == q1);
+        if (pos < A.cap) {
+            store_child_q(A, q2, pos, t, o.ch[1]);
+            stores += 1;
+        } else {
+            atomicOr(&A.ctrl->overflow, 1u);
+        }
+    }
+    __syncthreads();
+}
+
+template <class P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_rk_resume(BatchArgs<P> A)
+{
+    __shared__ ScanShared<BLOCK> sh;
+    __shared__ unsigned cnt_lds[kNCount];
+    __shared__ unsigned long long rk_lds[2];
+    __shared__ DepCache dc;
+    for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
+    if (threadIdx.x < 2) rk_lds[threadIdx.x] = 0ull;
+    dep_clear<BLOCK>(dc);
+    const bool halt = A.ctrl->halt != 0;
+    const uint32_t ne = halt ? 0u : min(A.ctrl->rk_count[0], A.jcap);
+    const uint32_t np = halt ? 0u : min(A.ctrl->rk_count[1], A.jcap);
+    const uint32_t ce = (ne + BLOCK - 1) / BLOCK, cp = (np + BLOCK - 1) / BLOCK;
+    const uint32_t n_chunks = ce + cp;
+    const uint32_t participants = n_chunks < gridDim.x ? (n_chunks > 0 ? n_chunks : 1u) : gridDim.x;
+    if (blockIdx.x >= participants) return;
+    Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
+    uint32_t steps_e = 0, steps_p = 0, stores = 0;
+    RkSum rks{0u, 0u, 0u};
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = (int)atomicAdd(&A.ctrl->rk_ticket, 1u);
+        __syncthreads();
+        const uint32_t chunk = (uint32_t)sh.ticket;
+        __syncthreads();
+        if (chunk >= n_chunks) break;
+        if (chunk < ce)
+            resume_chunk<P, kElectron, BLOCK>(A, c, chunk * BLOCK, ne, sh, dc, cnt_lds, steps_e, stores, rks);
+        else
+            resume_chunk<P, kPositron, BLOCK>(A, c, (chunk - ce) * BLOCK, np, sh, dc, cnt_lds, steps_p, stores, rks);
+    }
+    atomicAdd(&cnt_lds[kCSteps + kElectron], steps_e);
+    atomicAdd(&cnt_lds[kCSteps + kPositron], steps_p);
+    atomicAdd(&cnt_lds[kCStores], stores);
+    if (rks.acc | rks.rej) {
+        atomicAdd(&rk_lds[0], (unsigned long long)rks.acc);
+        atomicAdd(&rk_lds[1], (unsigned long long)rks.rej);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNCount; i += BLOCK)
+        if (cnt_lds[i]) atomicAdd(&A.S.counters[i], (unsigned long long)cnt_lds[i]);
+    if (threadIdx.x < 2 && rk_lds[threadIdx.x]) atomicAdd(&A.S.counters[kCRkSub + threadIdx.x], rk_lds[threadIdx.x]);
+    // the last participant empties the integration queue for the next launch
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t d = atomicAdd(&A.ctrl->rk_done, 1u);
+        if (d == participants - 1) {
+            __threadfence();
+            A.ctrl->rk_count[0] = 0;
+            A.ctrl->rk_count[1] = 0;
+            A.ctrl->rk_grab = 0;
+            A.ctrl->rk_ticket = 0;
+            A.ctrl->rk_done = 0;
+            __threadfence();
+        }
+    }
 }
 
 // ===========================================================================

@@ -175,6 +175,8 @@ struct Lib {
     DBuf<unsigned long long> esc_hist;
     DBuf<unsigned long long> trace_n;
     DBuf<unsigned long long> snap;   // counters, escape histogram, trace count before a window
+    DBuf<char> rk_jobs;              // integration queue (two arrays of RkJob, one per charged type)
+    uint32_t rk_jcap = 0;            // its capacity per type
     DBuf<PrimDev> prim;
     DBuf<uint32_t> prim_slot;
     Ctrl* h_ctrl = nullptr;  // pinned
@@ -287,6 +289,8 @@ void release_all()
     L.esc_hist.release();
     L.trace_n.release();
     L.snap.release();
+    L.rk_jobs.release();
+    L.rk_jcap = 0;
     L.prim.release();
     L.prim_slot.release();
     if (L.h_ctrl) (void)hipHostFree(L.h_ctrl);
@@ -622,6 +626,8 @@ int upload_ctrl(const uint32_t counts[3], uint64_t seed)
         c.count[1][t] = 0;
     }
     c.count[0][3] = c.count[1][3] = 0;
+    c.rk_count[0] = c.rk_count[1] = 0;
+    c.rk_grab = c.rk_ticket = c.rk_done = 0;
     c.ticket = 0;
     c.overflow = 0;
     c.done = 0;
@@ -700,6 +706,52 @@ template <class P> void launch_step_dispatch(int block, const BatchArgs<P>& A, i
     else launch_step_block<P, false>(block, A, grid, stable, s);
 }
 
+// RK45 with arrival-order queues runs its integrations through the
+// integration queue: the step kernel parks charged steps at their move, the
+// integration kernel runs them with lane refill, the resume kernel finishes them.
+bool rk_queue_mode()
+{
+    return L.cfg.driver == GV_DRIVER_BATCHED && L.cfg.field_method == GV_FIELD_RK45 &&
+           L.cfg.queue_order == GV_ORDER_ARRIVAL;
+}
+
+template <class P> void launch_rk_queue_step(int block, const BatchArgs<P>& A, int grid, hipStream_t s)
+{
+    switch (block) {
+    case 64:
+        k_step_batched<P, 64, false, true, true><<<grid, 64, 0, s>>>(A);
+        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
+        k_rk_resume<P, 64><<<grid, 64, 0, s>>>(A);
+        break;
+    case 128:
+        k_step_batched<P, 128, false, true, true><<<grid, 128, 0, s>>>(A);
+        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
+        k_rk_resume<P, 128><<<grid, 128, 0, s>>>(A);
+        break;
+    default:
+        k_step_batched<P, 256, false, true, true><<<grid, 256, 0, s>>>(A);
+        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
+        k_rk_resume<P, 256><<<grid, 256, 0, s>>>(A);
+        break;
+    }
+}
+
+// per-type capacity of the integration queue: the charged tracks one launch
+// can park (a launch that parks more overflows and the window reruns with
+// fewer events, as for the track queues)
+constexpr size_t kRkMaxJobs = (size_t)1 << 23;
+template <class P> int ensure_rk_jobs(size_t cap)
+{
+    const uint32_t jcap = (uint32_t)std::min(cap, kRkMaxJobs);
+    const size_t bytes = 2 * (size_t)jcap * sizeof(RkJob<P>);
+    if (L.rk_jobs.n < bytes || L.rk_jcap != jcap) {
+        drop_graph();
+        HIPCHK(L.rk_jobs.ensure(bytes));
+        L.rk_jcap = jcap;
+    }
+    return GV_OK;
+}
+
 template <class P> QueueMem<P>& batch_queues();
 template <> QueueMem<P64>& batch_queues<P64>() { return L.q64; }
 template <> QueueMem<PMix>& batch_queues<PMix>() { return L.qmix; }
@@ -730,12 +782,18 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
         A[par].tail_threshold = tu.tail;
         A[par].S = make_sinks();
         A[par].tv = tab_view<typename P::R>();
+        RkJob<P>* jobs = (RkJob<P>*)L.rk_jobs.p;
+        A[par].jobs[0] = jobs;
+        A[par].jobs[1] = jobs ? jobs + L.rk_jcap : nullptr;
+        A[par].jcap = jobs ? L.rk_jcap : 0u;
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
+    const bool rkq = rk_queue_mode();
     for (int k = 0; k < K; ++k) {
         if (helper) k_vacuum_helper<P><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
-        launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
+        if (rkq) launch_rk_queue_step<P>(tu.block, A[k & 1], grid, s);
+        else launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
     }
     hipError_t ce = hipStreamEndCapture(s, g);
     if (ce != hipSuccess) return fail(GV_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
@@ -1047,6 +1105,10 @@ template <class P> int transport_batched(int64_t n_events, uint64_t seed)
         L.q64.release();
         L.qmix.release();
         HIPCHK(Q.alloc(cap, 6, false));
+    }
+    if (rk_queue_mode()) {
+        const int rc0 = ensure_rk_jobs<P>(cap);
+        if (rc0) return rc0;
     }
     std::array<int, 3> choice{kDefBasket, kDefOccupancy, kDefInner};
     int rc = tuned_choice<P>(n_events, seed, choice);
@@ -1376,6 +1438,7 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     L.stats.rk_rejected = (int64_t)cnt[kCRkRej];
     L.stats.rk_lane_slots = (int64_t)cnt[kCRkSlots];
     L.stats.lane_slots = (int64_t)cnt[kCLaneSlots];
+    L.stats.helper_steps = (int64_t)cnt[kCHelperSteps];
     L.stats.trace_records = (int64_t)std::min<unsigned long long>(tn, (unsigned long long)L.cfg.trace_cap);
     L.stats.e_in = L.e_in;
     double ed = 0.0, es = 0.0, ek = 0.0, np_ = 0.0, na = 0.0;

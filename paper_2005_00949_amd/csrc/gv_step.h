@@ -238,8 +238,12 @@ __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 // HELIX); INTEG = true adds the RK4 and RK45 integrators, which run in double
 // in both precision policies.  VAC (a volume without material in a uniform
 // field) leaves out the field-map evaluation.
-template <class P, bool INTEG, bool VAC = false, class R = typename P::R>
-__device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
+// PARK: an RK45 move is not integrated here; the function returns true with
+// the step's length and nominal limiter in pr and the track unmoved, and
+// stage_move_resume finishes the move from the integrated end point (the
+// batched driver's integration queue).
+template <class P, bool INTEG, bool VAC = false, bool PARK = false, class R = typename P::R>
+__device__ inline bool stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
 #pragma clang fp contract(off)
     const DevGeom& g = *c.g;
@@ -280,7 +284,7 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
             t.vol = G.next;
             pr.crossed = 1;
         }
-        return;
+        return false;
     }
     // charged particle in a field
     const R p = m_sqrt(t.T * (t.T + (R)(2.0 * kMe)));
@@ -305,6 +309,7 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     }
     if (pr.lim == kLimGeom) pr.s += c.ph->push;
     if (INTEG && c.ph->field_method != kFieldHelix) {
+        if (PARK && c.ph->field_method == kFieldRk45) return true;
         double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
         const double T = (double)t.T;
         if (c.ph->field_method == kFieldRk45) {
@@ -326,6 +331,36 @@ __device__ inline void stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
         helix_move<R>(t.type, t.T, bh, kB, pr.s, t.x, t.u);
     }
     const int nv = locate(g, t.x, t.vol, G.next);
+    if (nv != t.vol) {
+        t.vol = nv;
+        pr.lim = kLimGeom;
+        pr.crossed = 1;
+    }
+    return false;
+}
+
+// The end of a parked RK45 move (see stage_move): the integrated end point x,
+// unit direction u and length s_done, then relocation, as stage_move does
+// after its own integration.  pr holds the parked step's length and limiter.
+template <class P, class R = typename P::R>
+__device__ inline void stage_move_resume(const Ctx<P>& c, Track<P>& t, const Geo& G, Prop<R>& pr, const double x[3],
+                                         const double u[3], double s_done, int acc, int rej)
+{
+    pr.T_pre = t.T;
+    pr.crossed = 0;
+    pr.rk.acc = acc;
+    pr.rk.rej = rej;
+    pr.rk.iters = 0;
+    if (s_done < pr.s) {  // attempts ran out: the step ends where integration stopped
+        pr.s = s_done;
+        pr.lim = kLimField;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        t.x[a] = x[a];
+        t.u[a] = (R)u[a];
+    }
+    const int nv = locate(*c.g, t.x, t.vol, G.next);
     if (nv != t.vol) {
         t.vol = nv;
         pr.lim = kLimGeom;
@@ -518,6 +553,23 @@ __device__ inline void stage_finish(const Ctx<P>& c, Track<P>& t, const Limits<R
 // checks this); WORLD: in the world volume.  It runs the same stage code
 // with the material branches decided at compile time, so it takes exactly the
 // steps of the general form.
+// the stages after Propagation
+template <class P, class R = typename P::R>
+__device__ __forceinline__ void step_after_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G,
+                                                const Prop<R>& pr, StepOut<R>& o)
+{
+    o.did_step = 1;
+    o.s = pr.s;
+    o.lim = pr.lim;
+    o.s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
+    o.d_bnd = G.d_bnd;
+    o.safety = G.safety;
+    o.rk = pr.rk;
+    stage_msc(c, t, L, pr);
+    const bool stopped = stage_eloss(c, t, L, pr, o);
+    stage_finish(c, t, L, pr, stopped, o);
+}
+
 template <class P, bool INTEG, bool VAC = false, bool WORLD = false, class R = typename P::R>
 __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
 {
@@ -530,16 +582,288 @@ __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
     stage_geom<P, WORLD>(c, t, G);
     Prop<R> pr;
     stage_move<P, INTEG, VAC>(c, t, L, G, pr);
+    step_after_move(c, t, L, G, pr, o);
+}
+
+// The same step, stopped at an RK45 move (returns true: the track is unmoved
+// and L, G, pr hold what the rest of the step needs); any other step is taken
+// whole (returns false).
+template <class P, class R = typename P::R>
+__device__ inline bool step_track_park(const Ctx<P>& c, Track<P>& t, StepOut<R>& o, Limits<R>& L, Geo& G, Prop<R>& pr)
+{
+    init_out(t, o);
+    if (!stage_prestep(c, t, o)) return false;
+    stage_limit<P>(c, t, L);
+    stage_geom<P>(c, t, G);
+    if (stage_move<P, true, false, true>(c, t, L, G, pr)) return true;
+    step_after_move(c, t, L, G, pr, o);
+    return false;
+}
+
+// The rest of a parked step from its integration result.
+template <class P, class R = typename P::R>
+__device__ inline void step_track_resume(const Ctx<P>& c, Track<P>& t, StepOut<R>& o, const Limits<R>& L, const Geo& G,
+                                         Prop<R>& pr, const double x[3], const double u[3], double s_done, int acc,
+                                         int rej)
+{
+    init_out(t, o);
+    stage_move_resume(c, t, G, pr, x, u, s_done, acc, rej);
+    step_after_move(c, t, L, G, pr, o);
+}
+
+// ---- charged tracks in the vacuum world: the looper form ------------------
+// A charged track in the world volume of a slab stack, in a uniform field
+// with the helix, takes exactly the step of step_track<P, false, true, true>
+// (the same expressions in the same order, so the same bits), with savings
+// that matter for the low-population tail, where such tracks step one after
+// another along a dependent chain:
+//   * what vacuum does not change is formed once per run of steps (the
+//     momentum and the helix phase per unit length from the kinetic energy,
+//     which no vacuum step alters; field and cut constants);
+//   * work whose outcome is already decided is skipped.  A ray leaves the
+//     world box no sooner than the distance to its nearest wall, and enters
+//     the envelope box no sooner than the distance to that box, so when
+//     either distance certainly exceeds the field step its candidate is not
+//     formed; a candidate that is formed is divided out only if it may be
+//     the shorter; the square root of the distance to the envelope is taken
+//     only if the safety may exceed the bending estimate.  "Certainly" holds
+//     with a margin far above the worst rounding of the quantities compared
+//     (2^-40 for quotients and roots, 2^-16 for the distance bounds, which
+//     also absorb the rounding of a float direction's length).
+template <class P> struct WorldRun {
+    using R = typename P::R;
+    double kq;        // -(q kB / p): helix phase per unit length
+    R pf;             // momentum in the policy's precision (bending radius)
+    R kBf, chord;     // curvature constant and bending tolerance
+    R b[3];           // field direction
+    double push;
+};
+
+template <class P, class R = typename P::R>
+__device__ __forceinline__ WorldRun<P> world_run(const Ctx<P>& c, const Track<P>& t)
+{
+#pragma clang fp contract(off)
+    WorldRun<P> k;
+    const DevGeom& g = *c.g;
+    const double q = t.type == kElectron ? -1.0 : 1.0;
+    const double Td = (double)t.T;
+    const double p = sqrt(Td * (Td + 2.0 * kMe));
+    k.kq = -(q * g.kB / p);
+    k.pf = m_sqrt(t.T * (t.T + (R)(2.0 * kMe)));
+    k.kBf = (R)g.kB;
+    k.chord = (R)c.ph->chord_tol;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) k.b[a] = (R)g.Bhat[a];
+    k.push = c.ph->push;
+    return k;
+}
+
+// true only if fl(num / den) > cap is certain (num, den > 0)
+__device__ __forceinline__ bool quotient_beyond(double num, double den, double cap)
+{
+#pragma clang fp contract(off)
+    const double lim = cap * den;
+    return lim > 0x1p-1000 && num > lim * (1.0 + 0x1p-40);
+}
+
+// true only if fl(sqrt(q)) < d is certain
+__device__ __forceinline__ bool root_below(double q, double d)
+{
+#pragma clang fp contract(off)
+    return q <= (d * d) * (1.0 - 0x1p-40);
+}
+
+// The candidates of slab_world without their divisions: entry into the
+// envelope box at nn / nd (valid if `entry`), exit from the world box at wn / wd.
+struct WorldCand {
+    double nn, nd, wn, wd;
+    int an;
+    bool entry;
+};
+
+__device__ __forceinline__ void world_entry(const DevGeom& g, const double p[3], const double d[3], WorldCand& w)
+{
+#pragma clang fp contract(off)
+    const double lo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
+    const double hi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
+    double nn = -1.0, nd = 0.0, fn = 1.0, fd = 0.0;
+    int an = -1;
+    bool miss = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool moving = d[a] != 0.0;
+        const bool up = d[a] > 0.0;
+        const double den = fabs(d[a]);
+        const double n_near = up ? lo[a] - p[a] : p[a] - hi[a];
+        const double n_far = up ? hi[a] - p[a] : p[a] - lo[a];
+        miss = miss | (!moving & ((p[a] < lo[a]) | (p[a] > hi[a])));
+        const bool tn = moving & (n_near * nd > nn * den);
+        const bool tf = moving & (n_far * fd < fn * den);
+        nn = tn ? n_near : nn;
+        nd = tn ? den : nd;
+        an = tn ? a : an;
+        fn = tf ? n_far : fn;
+        fd = tf ? den : fd;
+    }
+    w.nn = nn;
+    w.nd = nd;
+    w.an = an;
+    w.entry = nd != 0.0 && !miss && nn * fd <= fn * nd && fn > 0.0;
+}
+
+__device__ __forceinline__ void world_exit(const DevGeom& g, const double p[3], const double d[3], WorldCand& w)
+{
+#pragma clang fp contract(off)
+    const double wlo[3] = {-g.world[0], -g.world[1], g.world[2]};
+    const double whi[3] = {g.world[0], g.world[1], g.world[3]};
+    double wn = 1.0, wd = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool up = d[a] > 0.0;
+        const double n = up ? whi[a] - p[a] : p[a] - wlo[a];
+        const double den = fabs(d[a]);
+        const bool take = (d[a] != 0.0) & (n * wd < wn * den);
+        wn = take ? n : wn;
+        wd = take ? den : wd;
+    }
+    w.wn = wn;
+    w.wd = wd;
+}
+
+template <class P, class R = typename P::R>
+__device__ inline void step_world(const Ctx<P>& c, const WorldRun<P>& k, Track<P>& t, StepOut<R>& o)
+{
+#pragma clang fp contract(off)
+    const DevGeom& g = *c.g;
+    if (g.axis != 0 || g.Bmag == 0.0 || t.vol != 0 || t.type == kGamma || t.T < (R)c.ph->t_track ||
+        (long long)t.nstep >= c.ph->max_steps) {
+        step_track<P, false, true, true>(c, t, o);
+        return;
+    }
+    init_out(t, o);
+    const double p[3] = {t.x[0], t.x[1], t.x[2]};
+    const double d[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
+    // bending estimate (stage_move)
+    const R cx = t.u[1] * k.b[2] - t.u[2] * k.b[1], cy = t.u[2] * k.b[0] - t.u[0] * k.b[2],
+            cz = t.u[0] * k.b[1] - t.u[1] * k.b[0];
+    const R sin2 = cx * cx + cy * cy + cz * cz;
+    double dfield = kInf;
+    if (sin2 > (R)0) {
+        const R rc = k.pf / (k.kBf * m_sqrt(sin2));
+        dfield = (double)m_sqrt((R)2 * rc * k.chord);
+    }
+    // safety (slab_world_safety): the world's walls, then the envelope box
+    double walls = fmin(g.world[0] - fabs(p[0]), g.world[1] - fabs(p[1]));
+    walls = fmin(walls, fmin(p[2] - g.world[2], g.world[3] - p[2]));
+    const double zc = 0.5 * (g.bounds[0] + g.bounds[g.n_vol]);
+    const double zh = 0.5 * (g.bounds[g.n_vol] - g.bounds[0]);
+    const double qx = fmax(fabs(p[0]) - g.env[0], 0.0);
+    const double qy = fmax(fabs(p[1]) - g.env[1], 0.0);
+    const double qz = fmax(fabs(p[2] - zc) - zh, 0.0);
+    const double qq = qx * qx + qy * qy + qz * qz;
+    double cap;
+    if (walls <= dfield || root_below(qq, dfield)) {
+        cap = dfield;   // the safety does not exceed the bending estimate
+    } else {
+        double sf = fmin(walls, sqrt(qq));
+        sf = sf > 0.0 ? sf : 0.0;
+        cap = fmax(dfield, sf);
+    }
+    // boundary candidates along the ray (slab_world), formed only where they
+    // may be shorter than the field step.  A ray that is outside the
+    // envelope's extent along some axis and does not move towards it there
+    // never enters (slab_world then finds no valid entry either: the far
+    // candidate of that axis is negative, or the axis misses).
+    const double elo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
+    const double ehi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
+    bool away = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) away = away | ((p[a] > ehi[a]) & (d[a] >= 0.0)) | ((p[a] < elo[a]) & (d[a] <= 0.0));
+    const bool env_far = away || qq > (cap * cap) * (1.0 + 0x1p-14);
+    const bool walls_far = walls > cap * (1.0 + 0x1p-16);
+    WorldCand w;
+    w.entry = false;
+    if (!env_far) world_entry(g, p, d, w);
+    const bool entry_far = env_far || !w.entry || (w.nn > 0.0 && quotient_beyond(w.nn, w.nd, cap));
+    bool exit_far = walls_far;
+    if (!exit_far) {
+        world_exit(g, p, d, w);
+        exit_far = w.wd > 0.0 && quotient_beyond(w.wn, w.wd, cap);
+    }
+    double s;
+    int lim;
+    int next = 0;
+    if (entry_far && exit_far) {
+        s = cap;                  // every boundary lies beyond the field step
+        lim = kLimField;
+        o.d_bnd = kInf;
+    } else {
+        // the exact boundary distance, as slab_world (a ray moving away finds
+        // no valid entry there, so none is formed)
+        if (env_far && !away) world_entry(g, p, d, w);
+        if (walls_far) world_exit(g, p, d, w);
+        double dt = kInf;
+        if (w.entry) {
+            dt = w.nn > 0.0 ? w.nn / w.nd : 0.0;
+            next = (w.nn > 0.0 && w.an == 2) ? (d[2] > 0.0 ? 1 : g.n_vol) : 0;   // a guess for relocation
+        }
+        double tw = w.wd > 0.0 ? w.wn / w.wd : kInf;
+        tw = tw > 0.0 ? tw : 0.0;
+        if (!(dt <= tw)) {
+            dt = tw;
+            next = 0;
+        }
+        o.d_bnd = dt;
+        const double s0 = fmin(kInf, dt);
+        if (s0 <= cap) {
+            s = s0;
+            lim = kLimGeom;
+        } else {
+            s = cap;
+            lim = kLimField;
+        }
+        if (lim == kLimGeom) s += k.push;
+    }
+    // helix (helix_move) with the run's phase per unit length
+    {
+        const double th = k.kq * s;
+        const double thr = sizeof(R) == sizeof(double) ? th : th - 2.0 * kPi * rint(th * (0.5 / kPi));
+        const R upar = t.u[0] * k.b[0] + t.u[1] * k.b[1] + t.u[2] * k.b[2];
+        const R up[3] = {t.u[0] - upar * k.b[0], t.u[1] - upar * k.b[1], t.u[2] - upar * k.b[2]};
+        const R bxu[3] = {k.b[1] * up[2] - k.b[2] * up[1], k.b[2] * up[0] - k.b[0] * up[2],
+                          k.b[0] * up[1] - k.b[1] * up[0]};
+        const R sn = m_sin((R)thr), hs = m_sin((R)(0.5 * thr));
+        const R omc = (R)2 * hs * hs;
+        R f1, f2;
+        if (fabs(th) < 1.0e-4) {
+            f1 = (R)(1.0 - th * th / 6.0);
+            f2 = (R)(0.5 * th);
+        } else {
+            f1 = sn / (R)th;
+            f2 = omc / (R)th;
+        }
+        const R cs = (R)1 - omc;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            t.x[a] += s * (double)(upar * k.b[a] + f1 * up[a] + f2 * bxu[a]);
+            t.u[a] = upar * k.b[a] + cs * up[a] + sn * bxu[a];
+        }
+        normalise(t.u);
+    }
+    const int nv = locate(g, t.x, 0, next);
+    if (nv != 0) {
+        t.vol = nv;
+        lim = kLimGeom;
+    }
     o.did_step = 1;
-    o.s = pr.s;
-    o.lim = pr.lim;
-    o.s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
-    o.d_bnd = G.d_bnd;
-    o.safety = G.safety;
-    o.rk = pr.rk;
-    stage_msc(c, t, L, pr);
-    const bool stopped = stage_eloss(c, t, L, pr, o);
-    stage_finish(c, t, L, pr, stopped, o);
+    o.s = s;
+    o.lim = lim;
+    o.s_phys = kInf;
+    if (t.vol == kOutside) {
+        o.e_escaped += (double)t.T;
+        o.status = kEscaped;
+    }
+    t.nstep += 1;
 }
 
 }  // namespace gv
