@@ -455,6 +455,31 @@ typedef struct {
  * up), GV_E_HIP. */
 int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io);
 
+/* gv_compact3_noalloc -- the three-way stable compaction of GV_DBG_COMPACT
+ * (queue management of the stage baskets) for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  It calls no hipMalloc, hipFree, hipMemset or
+ * allocating library routine; its working memory (basket ticket and
+ * look-back status words, 6 MiB) is a static array of the library, one copy
+ * per device, held until the process ends, and cleared by a kernel at the
+ * start of every call.  Calls that overlap on one device share that array
+ * and race: serialise them (one stream, or events).  Does not need gv_init.
+ *   codes: device array of 3n int8 in {-1, 0, 1, 2}: the output queue of the
+ *     survivor and the two secondary slots of each input (-1 = none).
+ *   n: 0 <= n <= 2^24 (the scratch limit); block: 64, 128 or 256.
+ *   index: device array of 9n int32; queue q receives input*4 + slot, in
+ *     input order then slot order, at index[q*3n ...]; entries past the
+ *     queue's count are left unwritten.
+ *   counts: device array of 4 uint32: the three queue sizes, then error
+ *     flags (bit 1: a look-back wait gave up, bit 2: a code outside [-1, 2],
+ *     which is dropped).
+ *   hip_stream: hipStream_t to run on (NULL = the null stream).  The call
+ *     only enqueues work: results are ready when the stream reaches them.
+ * Errors (nothing enqueued): GV_E_INVALID_ARG (n out of range, block, null
+ * pointer, device index >= 64), GV_E_HIP. */
+int gv_compact3_noalloc(const int8_t* codes, int64_t n, int32_t block, int32_t* index, uint32_t* counts,
+                        void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

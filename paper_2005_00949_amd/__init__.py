@@ -130,6 +130,7 @@ def load():
     lib.gv_debug_step.argtypes = [C.c_int32, C.c_int64, C.POINTER(DebugIO)]
     lib.gv_alias_table.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gv_escape_hist.argtypes = [C.c_void_p, C.c_int64]
+    lib.gv_compact3_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     _lib = lib
     return lib
 
@@ -153,6 +154,15 @@ def _material(md) -> Material:
 
 def _p(a):
     return a.ctypes.data if a is not None else None
+
+
+def compact3_noalloc(codes_ptr, n, block, index_ptr, counts_ptr, stream=None):
+    """gv_compact3_noalloc on device buffers given as raw device pointers
+    (codes: 3n int8, index: 9n int32, counts: 4 uint32); enqueued on
+    `stream` (a hipStream_t as an integer, or None for the null stream)."""
+    lib = load()
+    _check(lib.gv_compact3_noalloc(C.c_void_p(codes_ptr), n, block, C.c_void_p(index_ptr), C.c_void_p(counts_ptr),
+                                   C.c_void_p(stream) if stream else None))
 
 
 class Engine:

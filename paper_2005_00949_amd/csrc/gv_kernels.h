@@ -586,7 +586,12 @@ __global__ void __launch_bounds__(BLOCK) k_dbg_compact(const int8_t* codes, long
         const long long i = chunk * BLOCK + threadIdx.x;
         int code[3] = {-1, -1, -1};
         if (i < n)
-            for (int j = 0; j < 3; ++j) code[j] = codes[3 * i + j];
+            for (int j = 0; j < 3; ++j) {
+                const int c = codes[3 * i + j];
+                // a code outside [-1, 2] is reported (bit 2) and dropped
+                if (c < -1 || c > 2) atomicOr(err, 4u);
+                code[j] = (c < -1 || c > 2) ? -1 : c;
+            }
         int cnt[3] = {0, 0, 0};
         for (int j = 0; j < 3; ++j)
             if (code[j] >= 0) cnt[code[j]]++;

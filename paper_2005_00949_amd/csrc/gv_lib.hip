@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1185,6 +1186,41 @@ int transport_plain(int64_t n_events, uint64_t seed)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Three-way compaction without allocation.  Its working memory (the basket
+// ticket and the look-back status words) lives in `scratch`, one copy per
+// device holding the library, kept until the process ends; the caller brings
+// inputs and outputs.  Host code reaches the array only through the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNaMaxInputs = (int64_t)1 << 24;                        // inputs per call
+constexpr size_t kNaHeader = 8;                                           // words before the status words
+constexpr size_t kNaStatus = 3 * (size_t)((kNaMaxInputs + 63) / 64);      // at the smallest block
+constexpr size_t kNaWords = kNaHeader + kNaStatus;                        // 6 MiB
+constexpr int kNaMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) uint64_t scratch[kNaWords];
+
+namespace {
+struct NaDevice {
+    uint64_t* ptr = nullptr;   // device address of this device's `scratch`
+    int n_cu = 0;
+};
+NaDevice g_na[kNaMaxDevices];
+std::mutex g_na_mutex;
+
+// zero the ticket, the caller's counts and the status words one call uses
+__global__ void k_na_clear(uint64_t* base, size_t status_words, uint32_t* counts)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNaHeader) base[i] = 0;
+    if (i < 4) counts[i] = 0;
+    for (size_t k = i; k < status_words; k += (size_t)gridDim.x * blockDim.x) base[kNaHeader + k] = 0;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1566,6 +1602,45 @@ void gv_finalize(void)
 {
     if (L.busy) return;
     release_all();
+}
+
+int gv_compact3_noalloc(const int8_t* codes, int64_t n, int32_t block, int32_t* index, uint32_t* counts,
+                        void* hip_stream)
+{
+    if (n < 0 || n > kNaMaxInputs) return fail(GV_E_INVALID_ARG, "n must be in [0, 2^24] (the scratch limit)");
+    if (block != 64 && block != 128 && block != 256) return fail(GV_E_INVALID_ARG, "block must be 64, 128 or 256");
+    if (!counts || (n > 0 && (!codes || !index))) return fail(GV_E_INVALID_ARG, "null device pointer");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(GV_E_INVALID_ARG, "device index beyond the supported range");
+    NaDevice d;
+    {
+        std::lock_guard<std::mutex> lock(g_na_mutex);
+        if (!g_na[dev].ptr) {
+            void* p = nullptr;
+            HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            int ncu = 0;
+            HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+            g_na[dev].n_cu = ncu > 0 ? ncu : 256;
+            g_na[dev].ptr = (uint64_t*)p;
+        }
+        d = g_na[dev];
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const long long nch = (n + block - 1) / block;
+    const size_t words = 3 * (size_t)nch;
+    const unsigned cg = (unsigned)std::max<size_t>(1, std::min<size_t>((words + 255) / 256, 1024));
+    k_na_clear<<<cg, 256, 0, s>>>(d.ptr, words, counts);
+    HIPCHK(hipGetLastError());
+    if (n == 0) return GV_OK;
+    uint32_t* ticket = (uint32_t*)d.ptr;
+    uint64_t* status = d.ptr + kNaHeader;
+    const unsigned grid = (unsigned)std::min<long long>(nch, (long long)d.n_cu * 4);
+    if (block == 64) k_dbg_compact<64><<<grid, 64, 0, s>>>(codes, n, index, 3 * n, counts, ticket, status, 1u);
+    else if (block == 128) k_dbg_compact<128><<<grid, 128, 0, s>>>(codes, n, index, 3 * n, counts, ticket, status, 1u);
+    else k_dbg_compact<256><<<grid, 256, 0, s>>>(codes, n, index, 3 * n, counts, ticket, status, 1u);
+    HIPCHK(hipGetLastError());
+    return GV_OK;
 }
 
 int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
