@@ -798,20 +798,24 @@ __device__ inline void step_world(const Ctx<P>& c, const WorldRun<P>& k, Track<P
         lim = kLimField;
         o.d_bnd = kInf;
     } else {
-        // the exact boundary distance, as slab_world (a ray moving away finds
-        // no valid entry there, so none is formed)
-        if (env_far && !away) world_entry(g, p, d, w);
-        if (walls_far) world_exit(g, p, d, w);
+        // the exact boundary distance, as slab_world.  A candidate known to
+        // lie beyond the field step is also beyond the other one here (which
+        // may not exceed the field step by more than rounding), so it cannot
+        // be the distance and is not formed: with the walls far, the distance
+        // is the envelope entry; with the envelope far (or moved away from),
+        // the world exit.
         double dt = kInf;
-        if (w.entry) {
+        if (!env_far && w.entry) {
             dt = w.nn > 0.0 ? w.nn / w.nd : 0.0;
             next = (w.nn > 0.0 && w.an == 2) ? (d[2] > 0.0 ? 1 : g.n_vol) : 0;   // a guess for relocation
         }
-        double tw = w.wd > 0.0 ? w.wn / w.wd : kInf;
-        tw = tw > 0.0 ? tw : 0.0;
-        if (!(dt <= tw)) {
-            dt = tw;
-            next = 0;
+        if (!walls_far) {
+            double tw = w.wd > 0.0 ? w.wn / w.wd : kInf;
+            tw = tw > 0.0 ? tw : 0.0;
+            if (!(dt <= tw)) {
+                dt = tw;
+                next = 0;
+            }
         }
         o.d_bnd = dt;
         const double s0 = fmin(kInf, dt);
