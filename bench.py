@@ -131,6 +131,7 @@ def run_gpu(args):
     edep_first = None
     per_ms, tail_ms = [], []
     tail_steps, kern_ms = 0, []
+    helper_steps = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         eng.transport_staged(seed + k, edep.data_ptr())
@@ -144,6 +145,7 @@ def run_gpu(args):
         per_ms.append(st["transport_ms"])
         tail_ms.append(st["tail_kernel_ms"])
         tail_steps += st["tail_steps"]
+        helper_steps += st["helper_steps"]
         kern_ms.append(st["kernel_ms"])
         if k == 0:
             edep_first = edep.cpu().numpy()
@@ -155,7 +157,7 @@ def run_gpu(args):
     res = dict(steps=steps, primaries=prims, elapsed=elapsed, kernel_ms=kernel_ms, launches=launches,
                alg_bytes=alg_bytes, stats0=st0, n_events=n_events, median_ms=float(np.median(per_ms)),
                autotune_ms=tune_ms, tail_ms=tail_ms, per_ms=per_ms, lane_slots=lane_slots, warm_ms=warm_ms,
-               tail_steps=tail_steps, kern_ms=kern_ms, edep_first=edep_first)
+               tail_steps=tail_steps, kern_ms=kern_ms, edep_first=edep_first, helper_steps=helper_steps)
 
     # the same transport through gv_transport with host primaries and a host
     # edep_out (PCIe both ways); reported beside value, never as value
@@ -373,6 +375,10 @@ def run_field_map(args, gv, torch, cfg):
         leg = dict(steps_per_s=steps / sum(ts), ms_per_transport=float(np.median(ts)) * 1e3,
                    kernel_ms_per_transport=kms / reps, e_dep_GeV=float(st["e_dep"]) * 1e-3 / len(prim),
                    tail_kernel_ms=float(st["tail_kernel_ms"]))
+        # kernel time outside the low-population tail replays (the shower phase)
+        leg["shower_kernel_ms"] = leg["kernel_ms_per_transport"] - leg["tail_kernel_ms"]
+        if name != "helix":
+            leg["shower_kernel_vs_helix"] = leg["shower_kernel_ms"] / max(out["helix"]["shower_kernel_ms"], 1e-9)
         if name == "rk45":
             leg["integration"] = ("integration queue: charged steps parked at their RK45 move while the population "
                                   "fills the GPU, integrated by one kernel with lanes refilled at every attempt")
@@ -586,6 +592,7 @@ def main():
                                max((sum(res["kern_ms"]) - sum(res["tail_ms"])) * 1e-3, 1e-12)),
         "tail_fraction": sum(res["tail_ms"]) / max(sum(res["per_ms"]), 1e-12),
         "tail_steps_per_transport": res["tail_steps"] / args.steps,
+        "helper_steps_per_transport": res["helper_steps"] / args.steps,
         "edep_vs_oracle": vs_oracle,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": (value / plain["steps_per_s"]) if plain else None,

@@ -624,11 +624,34 @@ struct Ctrl {
     uint32_t pad;
     uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
     uint32_t rk_count[2];   // integration queue: moves parked in this launch, per charged type
+    uint32_t rk_heavy[2];   // ... of which long (above kRkFirstTurns), listed first in the integration order
+    uint32_t rk_light[2];   // ... and short, listed after them
     uint32_t rk_grab;       // next parked move for the integration kernel
     uint32_t rk_ticket;     // next chunk of parked moves for the resume kernel
     uint32_t rk_done;       // resume workgroups finished in this launch
     uint32_t pad2;
 };
+
+// Work of an RK45 move before it is integrated (Sec. 3.6 sorts field
+// propagation work by length over radius of curvature): its turning angle at
+// the start, s |q kKB B x u| / p, in units of the turning the integrator
+// allows one attempt, i.e. the number of attempts it needs at least.  Parked
+// moves of more than kRkFirstTurns are integrated before the others (the
+// paper's pre-processed baskets), so the queue drains on single-attempt moves
+// instead of waiting for a long integration that started last.
+constexpr double kRkFirstTurns = 1.0;
+
+template <class P, class R = typename P::R>
+__device__ __forceinline__ double rk_turns(const Track<P>& t, double s)
+{
+    R B[3];
+    field_at<R>(c_geom, t.x, B);
+    const R cx = t.u[1] * B[2] - t.u[2] * B[1], cy = t.u[2] * B[0] - t.u[0] * B[2], cz = t.u[0] * B[1] - t.u[1] * B[0];
+    const double bperp = sqrt((double)(cx * cx + cy * cy + cz * cz));
+    const double Td = (double)t.T;
+    const double theta = 0.8 * sqrt(sqrt(c_phys.rk_tol / kDpK));
+    return s * kKB * bperp / (theta * sqrt(Td * (Td + 2.0 * kMe)));
+}
 
 // A step parked at its RK45 move (the integration queue of the batched
 // driver): the track before the move, what the rest of the step needs, and
@@ -659,7 +682,8 @@ template <class P> struct BatchArgs {
     Sinks S;
     TabView<typename P::R> tv;
     RkJob<P>* jobs[2];       // integration queue per charged type (RK45 with arrival order)
-    uint32_t jcap;           // its capacity per type
+    uint32_t* order[2];      // integration order per type: long moves from the front, short ones from the back
+    uint32_t jcap;           // capacity per type of both
 };
 
 // Primary ingest (the event server of Sec. 2.1): validated, typed primaries
@@ -744,17 +768,19 @@ __device__ __forceinline__ int pick3(int q, const int v[3]) { return q == 0 ? v[
 // the same iteration reserve their slots with one atomic per wavefront).
 template <class P, int TY, class R = typename P::R>
 __device__ __forceinline__ void park_job(const BatchArgs<P>& A, const Track<P>& t, const Limits<R>& L, const Geo& G,
-                                         const Prop<R>& pr)
+                                         const Prop<R>& pr, double turns)
 {
+    static_assert(TY == kElectron || TY == kPositron, "only charged steps are parked");
+    constexpr int q = TY - 1;
     const uint64_t pm = __ballot(1);
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((unsigned long long)pm) - 1;
     uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&A.ctrl->rk_count[TY - 1], (uint32_t)__popcll(pm));
+    if (lane == leader) base = atomicAdd(&A.ctrl->rk_count[q], (uint32_t)__popcll(pm));
     base = (uint32_t)__shfl((int)base, leader, 64);
     const uint32_t k = base + (uint32_t)__popcll(pm & ((1ull << lane) - 1ull));
     if (k < A.jcap) {
-        RkJob<P>& J = A.jobs[TY - 1][k];
+        RkJob<P>& J = A.jobs[q][k];
         J.t = t;
         J.L = L;
         J.G = G;
@@ -763,6 +789,22 @@ __device__ __forceinline__ void park_job(const BatchArgs<P>& A, const Track<P>& 
     } else {
         atomicOr(&A.ctrl->overflow, 1u);
     }
+    // integration order: the longest moves are listed from the front of the
+    // order array, the others from its back (the two never meet: every stored
+    // move is listed once and at most jcap are stored)
+    const bool stored = k < A.jcap;
+    const bool heavy = stored && turns > kRkFirstTurns;
+    const uint64_t hm = __ballot(heavy), lm = __ballot(stored && !heavy);
+    uint32_t hb = 0, lb = 0;
+    if (lane == leader) {
+        if (hm) hb = atomicAdd(&A.ctrl->rk_heavy[q], (uint32_t)__popcll(hm));
+        if (lm) lb = atomicAdd(&A.ctrl->rk_light[q], (uint32_t)__popcll(lm));
+    }
+    hb = (uint32_t)__shfl((int)hb, leader, 64);
+    lb = (uint32_t)__shfl((int)lb, leader, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (heavy) A.order[q][hb + (uint32_t)__popcll(hm & below)] = k;
+    else if (stored) A.order[q][A.jcap - 1u - (lb + (uint32_t)__popcll(lm & below))] = k;
 }
 
 template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, bool PARK = false, class R = typename P::R>
@@ -827,7 +869,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                 Prop<R> pr;
                 iters += 1;
                 if (step_track_park(c, t, o, L, G, pr)) {
-                    park_job<P, TY>(A, t, L, G, pr);
+                    if constexpr (TY != kGamma) park_job<P, TY>(A, t, L, G, pr, rk_turns<P>(t, pr.s));
                     o.status = kParked;
                     break;
                 }
@@ -1082,6 +1124,9 @@ __global__ void __launch_bounds__(kRkBlock) k_rk_integrate(BatchArgs<P> A)
     const uint32_t ne = halt ? 0u : min(A.ctrl->rk_count[0], A.jcap);
     const uint32_t np = halt ? 0u : min(A.ctrl->rk_count[1], A.jcap);
     const uint32_t total = ne + np;
+    // integration order: long moves of both types, then short ones
+    const uint32_t he = halt ? 0u : min(A.ctrl->rk_heavy[0], ne), hp = halt ? 0u : min(A.ctrl->rk_heavy[1], np);
+    const uint32_t le = ne - he;
     const double tol = c_phys.rk_tol;
     const int max_sub = c_phys.rk_max_sub;
     const int lane = threadIdx.x & 63;
@@ -1103,7 +1148,12 @@ __global__ void __launch_bounds__(kRkBlock) k_rk_integrate(BatchArgs<P> A)
             if (!has) {
                 const uint32_t j = base + (uint32_t)__popcll(need & below);
                 if (j < total) {
-                    job = j < ne ? &A.jobs[0][j] : &A.jobs[1][j - ne];
+                    uint32_t ty, o;
+                    if (j < he) ty = 0, o = j;
+                    else if (j < he + hp) ty = 1, o = j - he;
+                    else if (j < he + hp + le) ty = 0, o = A.jcap - 1u - (j - he - hp);
+                    else ty = 1, o = A.jcap - 1u - (j - he - hp - le);
+                    job = &A.jobs[ty][A.order[ty][o]];
                     const Track<P>& t = job->t;
                     const double pos[3] = {t.x[0], t.x[1], t.x[2]};
                     const double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
@@ -1268,6 +1318,8 @@ __global__ void __launch_bounds__(BLOCK) k_rk_resume(BatchArgs<P> A)
             __threadfence();
             A.ctrl->rk_count[0] = 0;
             A.ctrl->rk_count[1] = 0;
+            A.ctrl->rk_heavy[0] = A.ctrl->rk_heavy[1] = 0;
+            A.ctrl->rk_light[0] = A.ctrl->rk_light[1] = 0;
             A.ctrl->rk_grab = 0;
             A.ctrl->rk_ticket = 0;
             A.ctrl->rk_done = 0;

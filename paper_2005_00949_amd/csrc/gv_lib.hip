@@ -628,6 +628,7 @@ int upload_ctrl(const uint32_t counts[3], uint64_t seed)
     }
     c.count[0][3] = c.count[1][3] = 0;
     c.rk_count[0] = c.rk_count[1] = 0;
+    c.rk_heavy[0] = c.rk_heavy[1] = c.rk_light[0] = c.rk_light[1] = 0;
     c.rk_grab = c.rk_ticket = c.rk_done = 0;
     c.ticket = 0;
     c.overflow = 0;
@@ -744,7 +745,7 @@ constexpr size_t kRkMaxJobs = (size_t)1 << 23;
 template <class P> int ensure_rk_jobs(size_t cap)
 {
     const uint32_t jcap = (uint32_t)std::min(cap, kRkMaxJobs);
-    const size_t bytes = 2 * (size_t)jcap * sizeof(RkJob<P>);
+    const size_t bytes = 2 * (size_t)jcap * (sizeof(RkJob<P>) + sizeof(uint32_t));
     if (L.rk_jobs.n < bytes || L.rk_jcap != jcap) {
         drop_graph();
         HIPCHK(L.rk_jobs.ensure(bytes));
@@ -786,6 +787,9 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
         RkJob<P>* jobs = (RkJob<P>*)L.rk_jobs.p;
         A[par].jobs[0] = jobs;
         A[par].jobs[1] = jobs ? jobs + L.rk_jcap : nullptr;
+        uint32_t* order = jobs ? (uint32_t*)(jobs + 2 * (size_t)L.rk_jcap) : nullptr;
+        A[par].order[0] = order;
+        A[par].order[1] = order ? order + L.rk_jcap : nullptr;
         A[par].jcap = jobs ? L.rk_jcap : 0u;
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
