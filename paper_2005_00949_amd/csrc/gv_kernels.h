@@ -1049,6 +1049,25 @@ k_step_batched(BatchArgs<P> A)
 // counters are the same as without the helper.  Any photon, track in
 // material or population above one workgroup makes it return at once.
 constexpr int kVacHelperBlock = 256;
+
+template <class P, bool TRACE, class R = typename P::R>
+__device__ __forceinline__ void helper_steps(const BatchArgs<P>& A, const Ctx<P>& c, const WorldRun<P>& run,
+                                             Track<P>& t, int max_steps, int& calls, int& kept)
+{
+    for (; calls < max_steps;) {
+        Track<P> tn = t;
+        StepOut<R> o;
+        const uint32_t ns = t.nstep;
+        if (t.vol == 0) step_world(c, run, tn, o);
+        else step_track<P, false, true>(c, tn, o);
+        calls += 1;
+        if (o.status != kAlive) break;
+        if (tn.vol != t.vol && vol_material(c_geom, tn.vol) >= 0) break;
+        if (TRACE && o.did_step) trace_step(A.S, tn, o.vol_pre, tn, o, ns);
+        t = tn;
+        kept += 1;
+    }
+}
 template <class P>
 __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> A, int max_steps)
 {
@@ -1073,21 +1092,12 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
     int calls = 0, kept = 0;
     if (active) {
-        // vacuum keeps the kinetic energy: the run constants hold for every kept step
+        // vacuum keeps the kinetic energy: the run constants hold for every
+        // kept step.  Without a trace the loop is its own copy, in which the
+        // step records' other fields are dead.
         const WorldRun<P> run = world_run(c, t);
-        for (; calls < max_steps;) {
-            Track<P> tn = t;
-            StepOut<R> o;
-            const uint32_t ns = t.nstep;
-            if (t.vol == 0) step_world(c, run, tn, o);
-            else step_track<P, false, true>(c, tn, o);
-            calls += 1;
-            if (o.status != kAlive) break;
-            if (tn.vol != t.vol && vol_material(c_geom, tn.vol) >= 0) break;
-            if (A.S.trace && o.did_step) trace_step(A.S, tn, o.vol_pre, tn, o, ns);
-            t = tn;
-            kept += 1;
-        }
+        if (A.S.trace) helper_steps<P, true>(A, c, run, t, max_steps, calls, kept);
+        else helper_steps<P, false>(A, c, run, t, max_steps, calls, kept);
         if (kept) {
             store_track(A.in[ty], slot, t);
             atomicAdd(&A.S.counters[kCSteps + ty], (unsigned long long)kept);

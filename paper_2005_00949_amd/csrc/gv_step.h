@@ -632,11 +632,14 @@ __device__ inline void step_track_resume(const Ctx<P>& c, Track<P>& t, StepOut<R
 //     also absorb the rounding of a float direction's length).
 template <class P> struct WorldRun {
     using R = typename P::R;
+    bool lean;        // the looper form applies (slab stack, field on, charged, above the tracking cut)
     double kq;        // -(q kB / p): helix phase per unit length
     R pf;             // momentum in the policy's precision (bending radius)
     R kBf, chord;     // curvature constant and bending tolerance
     R b[3];           // field direction
     double push;
+    double zlo, zhi;  // the envelope's extent along the stack
+    double zc, zh;    // ... as centre and half length
 };
 
 template <class P, class R = typename P::R>
@@ -645,6 +648,12 @@ __device__ __forceinline__ WorldRun<P> world_run(const Ctx<P>& c, const Track<P>
 #pragma clang fp contract(off)
     WorldRun<P> k;
     const DevGeom& g = *c.g;
+    // vacuum keeps the kinetic energy and the type: these tests hold for the run
+    k.lean = g.axis == 0 && g.Bmag != 0.0 && t.type != kGamma && !(t.T < (R)c.ph->t_track);
+    k.zlo = g.bounds[0];
+    k.zhi = g.bounds[g.n_vol];
+    k.zc = 0.5 * (g.bounds[0] + g.bounds[g.n_vol]);
+    k.zh = 0.5 * (g.bounds[g.n_vol] - g.bounds[0]);
     const double q = t.type == kElectron ? -1.0 : 1.0;
     const double Td = (double)t.T;
     const double p = sqrt(Td * (Td + 2.0 * kMe));
@@ -735,8 +744,7 @@ __device__ inline void step_world(const Ctx<P>& c, const WorldRun<P>& k, Track<P
 {
 #pragma clang fp contract(off)
     const DevGeom& g = *c.g;
-    if (g.axis != 0 || g.Bmag == 0.0 || t.vol != 0 || t.type == kGamma || t.T < (R)c.ph->t_track ||
-        (long long)t.nstep >= c.ph->max_steps) {
+    if (!k.lean || t.vol != 0 || (long long)t.nstep >= c.ph->max_steps) {
         step_track<P, false, true, true>(c, t, o);
         return;
     }
@@ -755,11 +763,9 @@ __device__ inline void step_world(const Ctx<P>& c, const WorldRun<P>& k, Track<P
     // safety (slab_world_safety): the world's walls, then the envelope box
     double walls = fmin(g.world[0] - fabs(p[0]), g.world[1] - fabs(p[1]));
     walls = fmin(walls, fmin(p[2] - g.world[2], g.world[3] - p[2]));
-    const double zc = 0.5 * (g.bounds[0] + g.bounds[g.n_vol]);
-    const double zh = 0.5 * (g.bounds[g.n_vol] - g.bounds[0]);
     const double qx = fmax(fabs(p[0]) - g.env[0], 0.0);
     const double qy = fmax(fabs(p[1]) - g.env[1], 0.0);
-    const double qz = fmax(fabs(p[2] - zc) - zh, 0.0);
+    const double qz = fmax(fabs(p[2] - k.zc) - k.zh, 0.0);
     const double qq = qx * qx + qy * qy + qz * qz;
     double cap;
     if (walls <= dfield || root_below(qq, dfield)) {
@@ -774,11 +780,10 @@ __device__ inline void step_world(const Ctx<P>& c, const WorldRun<P>& k, Track<P
     // envelope's extent along some axis and does not move towards it there
     // never enters (slab_world then finds no valid entry either: the far
     // candidate of that axis is negative, or the axis misses).
-    const double elo[3] = {-g.env[0], -g.env[1], g.bounds[0]};
-    const double ehi[3] = {g.env[0], g.env[1], g.bounds[g.n_vol]};
-    bool away = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) away = away | ((p[a] > ehi[a]) & (d[a] >= 0.0)) | ((p[a] < elo[a]) & (d[a] <= 0.0));
+    // (across the stack, outside the envelope's extent and moving away from it
+    // along that axis: |p| > env and p d >= 0, i.e. qx > 0 and p d >= 0)
+    const bool away = ((qx > 0.0) & (p[0] * d[0] >= 0.0)) | ((qy > 0.0) & (p[1] * d[1] >= 0.0)) |
+                      ((p[2] > k.zhi) & (d[2] >= 0.0)) | ((p[2] < k.zlo) & (d[2] <= 0.0));
     const bool env_far = away || qq > (cap * cap) * (1.0 + 0x1p-14);
     const bool walls_far = walls > cap * (1.0 + 0x1p-16);
     WorldCand w;
