@@ -28,8 +28,10 @@ def flags(debug: bool = False):
          "-ffp-contract=off",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         # float division and square root to within a few ulp (double stays IEEE)
-         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         # float division and square root to within a few ulp, float
+         # denormals (below 1.2e-38) flushed to zero: no range scaling around
+         # every float square root and reciprocal (double stays IEEE)
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", os.path.join(HERE, "..", "include")]
     if debug:
