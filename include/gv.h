@@ -379,7 +379,13 @@ enum {
     GV_DBG_PHILOX = 1,      /* raw Philox4x32-10 blocks */
     GV_DBG_COMPACT = 2,     /* stable three-way compaction (queue management) */
     GV_DBG_TABLE = 3,       /* read back a built table (node values) */
-    GV_DBG_GEOM = 4         /* distance to boundary, next volume, safety, locate */
+    GV_DBG_GEOM = 4,        /* distance to boundary, next volume, safety, locate */
+    /* the step of GV_DBG_STEP ended after one of its stages (Sec. 2.1.2): */
+    GV_DBG_THRU_LIMIT = 5,  /* ComputeIntLen: physics and continuous-loss lengths */
+    GV_DBG_THRU_GEOM = 6,   /* GeomQuery: boundary distance and safety */
+    GV_DBG_THRU_MOVE = 7,   /* Propagation: step length, limiter, moved and relocated track */
+    GV_DBG_THRU_MSC = 8,    /* PostPropagation: multiple-scattering deflection */
+    GV_DBG_THRU_ELOSS = 9   /* AlongStepAction: continuous energy loss and deposit */
 };
 
 /* Host arrays for the test entry point; which fields are read or written
@@ -394,7 +400,11 @@ enum {
  *                      (queue q at index + q*3n: input*4 + slot), counts[3]
  *   GV_DBG_TABLE  in : material, which (table id), precision;  out: values[n]
  *   GV_DBG_GEOM   in : pos, dir, vol (-2 = locate first);  out: d_bnd, vol (next),
- *                      vol_pre (located volume), safety */
+ *                      vol_pre (located volume), safety
+ *   GV_DBG_THRU_* in and out as GV_DBG_STEP, and out: s_eloss; outputs that the
+ *                      stages run so far have not produced keep their initial
+ *                      values (lengths 0, limiter and process -1, no children,
+ *                      the input position, direction and energy) */
 typedef struct {
     int32_t precision;
     int32_t block;
@@ -433,6 +443,7 @@ typedef struct {
     int32_t* index;
     int64_t* counts;
     double* values;
+    double* s_eloss;
 } gv_debug_io;
 
 /* gv_debug_step -- test entry point: run one stage on n independent inputs
@@ -448,7 +459,15 @@ typedef struct {
  *   GV_DBG_PHILOX  the counter-based generator of Sec. 3.3.2;
  *   GV_DBG_COMPACT the queue compaction of the stage baskets (Sec. 2.1.1);
  *   GV_DBG_TABLE   the built tables of Sec. 3.5;
- *   GV_DBG_GEOM    the geometry queries of Sec. 3.4.
+ *   GV_DBG_GEOM    the geometry queries of Sec. 3.4;
+ *   GV_DBG_THRU_*  the step of GV_DBG_STEP on the same inputs, ended after
+ *                  the named stage of Sec. 2.1.2, so that each stage's own
+ *                  outputs (ComputeIntLen and the continuous-loss limit of
+ *                  Sec. 3.5, the field rule and propagation of Sec. 3.4 and
+ *                  3.6, the deflection and loss of the along-step actions)
+ *                  are compared with those of the reference ended at the same
+ *                  stage; the discrete interaction and the stepping actions
+ *                  are those of the whole step.
  * GV_DBG_TABLE: n = number of nodes.  Uses temporary device allocations.
  * Errors: GV_E_INVALID_ARG (unknown stage, null or invalid inputs),
  * GV_E_NOT_INIT, GV_E_STATE (during a transport, or a look-back wait gave

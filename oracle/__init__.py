@@ -25,6 +25,9 @@ COUNTER_NAMES = (["steps_gamma", "steps_electron", "steps_positron",
                  + ["escaped", "killed", "rejection_exhausted", "trace_dropped",
                     "rk_substeps", "rk_rejected"])
 LEDGER_NAMES = ["escaped", "killed", "n_pair", "n_annih"]
+# single steps ended after one stage (Sec. 2.1.2): ComputeIntLen, GeomQuery,
+# Propagation, multiple scattering, continuous loss; 0 = the whole step
+STOP_LIMIT, STOP_GEOM, STOP_MOVE, STOP_MSC, STOP_ELOSS = 1, 2, 3, 4, 5
 TABLE_NAMES = ["compton", "pair", "moller", "brems_em", "S_em", "R_em",
                "bhabha", "brems_ep", "S_ep", "R_ep"]
 PDG_TO_TYPE = {22: GAMMA, 11: ELECTRON, -11: POSITRON}
@@ -83,6 +86,9 @@ def load(rebuild: bool = False):
     lib.or_single_step.argtypes = [C.c_int64, C.c_uint64, ip, dp, dp, dp, up32, up64, up32,
                                    dp, dp, dp, dp, ip, ip, ip, ip, ip, ip, ip, dp, dp, up64,
                                    dp, dp, dp, dp]
+    lib.or_stage_step.argtypes = [C.c_int32, C.c_int64, C.c_uint64, ip, dp, dp, dp, up32, up64, up32,
+                                  dp, dp, dp, dp, ip, ip, ip, ip, ip, ip, ip, dp, dp, up64,
+                                  dp, dp, dp, dp, dp]
     lib.or_philox4x32_10.argtypes = [up32, up32, up32]
     lib.or_stream.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, up32]
     for name in ["or_u53", "or_expo"]:
@@ -250,7 +256,9 @@ class Oracle:
         return out
 
     # ---- one step of independent tracks ----
-    def single_step(self, st, seed):
+    def single_step(self, st, seed, stop=0):
+        """One step of each state; stop = STOP_LIMIT ... STOP_ELOSS ends it
+        after that stage of Sec. 2.1.2 (the per-stage reference)."""
         n = len(st["type"])
         f64 = lambda *s: np.zeros(s, dtype=np.float64)
         i32 = lambda *s: np.zeros(s, dtype=np.int32)
@@ -258,7 +266,7 @@ class Oracle:
                  limiter=i32(n), process=i32(n), status=i32(n), n_children=i32(n),
                  ch_type=i32(n, 2), ch_ekin=f64(n, 2), ch_dir=f64(n, 2, 3),
                  ch_tid=np.zeros((n, 2), dtype=np.uint64), step=f64(n), s_phys=f64(n),
-                 d_bnd=f64(n), safety=f64(n))
+                 d_bnd=f64(n), safety=f64(n), s_eloss=f64(n))
         typ = np.ascontiguousarray(st["type"], dtype=np.int32)
         pos = np.ascontiguousarray(st["pos"], dtype=np.float64)
         dr = np.ascontiguousarray(st["dir"], dtype=np.float64)
@@ -267,13 +275,14 @@ class Oracle:
         tid = np.ascontiguousarray(st["tid"], dtype=np.uint64)
         ns = np.ascontiguousarray(st["nstep"], dtype=np.uint32)
         d, i, u32, u64 = C.c_double, C.c_int32, C.c_uint32, C.c_uint64
-        rc = self.lib.or_single_step(
-            n, seed, _ptr(typ, i), _ptr(pos, d), _ptr(dr, d), _ptr(ek, d), _ptr(ev, u32),
+        rc = self.lib.or_stage_step(
+            stop, n, seed, _ptr(typ, i), _ptr(pos, d), _ptr(dr, d), _ptr(ek, d), _ptr(ev, u32),
             _ptr(tid, u64), _ptr(ns, u32), _ptr(o["pos"], d), _ptr(o["dir"], d), _ptr(o["ekin"], d),
             _ptr(o["edep"], d), _ptr(o["vol"], i), _ptr(o["vol_pre"], i), _ptr(o["limiter"], i),
             _ptr(o["process"], i), _ptr(o["status"], i), _ptr(o["n_children"], i),
             _ptr(o["ch_type"], i), _ptr(o["ch_ekin"], d), _ptr(o["ch_dir"], d), _ptr(o["ch_tid"], u64),
-            _ptr(o["step"], d), _ptr(o["s_phys"], d), _ptr(o["d_bnd"], d), _ptr(o["safety"], d))
+            _ptr(o["step"], d), _ptr(o["s_phys"], d), _ptr(o["d_bnd"], d), _ptr(o["safety"], d),
+            _ptr(o["s_eloss"], d))
         if rc != 0:
             raise RuntimeError("oracle single step failed: " + self.lib.or_error().decode())
         return o

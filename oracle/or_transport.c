@@ -135,7 +135,7 @@ typedef struct {
 
 typedef struct {
     int32_t did_step, lim, proc, vol_pre, status, n_child;
-    double s, s_phys, d_bnd, safety, edep;
+    double s, s_phys, s_eloss, d_bnd, safety, edep;
     trk_t child[2];
 } step_t;
 
@@ -292,7 +292,10 @@ static void interact(uint64_t seed, uint32_t ev, trk_t* t, int first, step_t* si
     C[OR_C_PROC0 + si->proc] += 1;
 }
 
-static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L, int64_t* C)
+/* One step of one track in the stage order of Sec. 2.1.2.  stop > 0 ends
+ * it after the named stage (OR_STOP_*), with what that stage has produced
+ * so far: the per-stage reference of the single-step tests. */
+static void one_step_to(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L, int64_t* C, int stop)
 {
     const or_config* cf = &G.cfg;
     memset(si, 0, sizeof(*si));
@@ -349,12 +352,18 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
         s_eloss = (R <= R_FLOOR) ? R : fmax(R_FRAC * R, R_FLOOR);
     }
     const double s_lim = fmin(s_phys, s_eloss);
+    si->s_phys = s_phys;
+    si->s_eloss = s_eloss;
+    if (stop == OR_STOP_LIMIT) return;
 
     /* ---- GeomQuery ---- */
     int32_t next, snap_axis;
     double snap_val;
     const double d_bnd = or_dist_out_face(t->vol, t->pos, t->dir, &next, &snap_axis, &snap_val);
     const double safety = or_safety(t->vol, t->pos);
+    si->d_bnd = d_bnd;
+    si->safety = safety;
+    if (stop == OR_STOP_GEOM) return;
 
     /* ---- Propagation ---- */
     const double T_pre = t->T;
@@ -429,9 +438,7 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
     si->did_step = 1;
     si->s = s;
     si->lim = lim;
-    si->s_phys = s_phys;
-    si->d_bnd = d_bnd;
-    si->safety = safety;
+    if (stop == OR_STOP_MOVE) return;
 
     /* ---- PostPropagation: multiple scattering ---- */
     if (charged && m >= 0 && s > 0.0) {
@@ -445,6 +452,7 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
         double phi = atan2(ty, tx);
         or_rotate(t->dir, cos(th), sin(th), phi);
     }
+    if (stop == OR_STOP_MSC) return;
 
     /* ---- AlongStepAction: continuous loss ---- */
     int stopped = 0;
@@ -459,6 +467,7 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
         si->edep += dE;
         t->T = T_pre - dE;
     }
+    if (stop == OR_STOP_ELOSS) return;
 
     /* ---- PostStepActions: discrete interaction ---- */
     if (lim == OR_LIM_PHYS && !crossed && !stopped) {
@@ -477,6 +486,11 @@ static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L
     }
     C[OR_C_STEPS_G + t->type] += 1;
     t->nstep += 1;
+}
+
+static void one_step(uint64_t seed, uint32_t ev, trk_t* t, step_t* si, double* L, int64_t* C)
+{
+    one_step_to(seed, ev, t, si, L, C, 0);
 }
 
 /* ---------------- transport ---------------- */
@@ -698,8 +712,26 @@ int or_single_step(int64_t n, uint64_t seed,
                    int32_t* ch_type, double* ch_ekin, double* ch_dir, uint64_t* ch_tid,
                    double* s_out, double* sphys_out, double* dbnd_out, double* safety_out)
 {
+    return or_stage_step(0, n, seed, type, pos, dir, ekin, event, tid, nstep, pos_out, dir_out, ekin_out,
+                         edep_out, vol_out, vol_pre_out, lim_out, proc_out, status_out, nchild_out, ch_type,
+                         ch_ekin, ch_dir, ch_tid, s_out, sphys_out, dbnd_out, safety_out, NULL);
+}
+
+int or_stage_step(int32_t stop, int64_t n, uint64_t seed,
+                  const int32_t* type, const double* pos, const double* dir, const double* ekin,
+                  const uint32_t* event, const uint64_t* tid, const uint32_t* nstep,
+                  double* pos_out, double* dir_out, double* ekin_out, double* edep_out,
+                  int32_t* vol_out, int32_t* vol_pre_out, int32_t* lim_out, int32_t* proc_out,
+                  int32_t* status_out, int32_t* nchild_out,
+                  int32_t* ch_type, double* ch_ekin, double* ch_dir, uint64_t* ch_tid,
+                  double* s_out, double* sphys_out, double* dbnd_out, double* safety_out, double* seloss_out)
+{
     if (!G.ready) {
         or_set_error("not set up");
+        return -1;
+    }
+    if (stop < 0 || stop > OR_STOP_ELOSS) {
+        or_set_error("unknown stage");
         return -1;
     }
     for (int64_t i = 0; i < n; ++i) {
@@ -716,7 +748,7 @@ int or_single_step(int64_t n, uint64_t seed,
         double L[OR_NLEDGER] = {0};
         int64_t C[OR_NCOUNT] = {0};
         step_t si;
-        one_step(seed, event[i], &t, &si, L, C);
+        one_step_to(seed, event[i], &t, &si, L, C, stop);
         for (int a = 0; a < 3; ++a) {
             pos_out[3 * i + a] = t.pos[a];
             dir_out[3 * i + a] = t.dir[a];
@@ -747,6 +779,7 @@ int or_single_step(int64_t n, uint64_t seed,
         sphys_out[i] = si.s_phys;
         dbnd_out[i] = si.d_bnd;
         safety_out[i] = si.safety;
+        if (seloss_out) seloss_out[i] = si.s_eloss;
     }
     return 0;
 }

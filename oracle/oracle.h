@@ -160,6 +160,22 @@ int or_single_step(int64_t n, uint64_t seed,
                    int32_t* ch_type, double* ch_ekin, double* ch_dir, uint64_t* ch_tid,
                    double* s_out, double* sphys_out, double* dbnd_out, double* safety_out);
 
+/* the same step ended after one stage of Sec. 2.1.2 (stop = 0: the whole
+ * step, as or_single_step).  After ComputeIntLen: s_phys and s_eloss, the
+ * track unmoved; after GeomQuery: also d_bnd and safety; after Propagation:
+ * also the step length, limiter and the moved track (position, direction,
+ * volume); after multiple scattering: the deflected direction; after the
+ * continuous loss: the kinetic energy and deposit.  seloss_out may be NULL. */
+enum { OR_STOP_LIMIT = 1, OR_STOP_GEOM = 2, OR_STOP_MOVE = 3, OR_STOP_MSC = 4, OR_STOP_ELOSS = 5 };
+int or_stage_step(int32_t stop, int64_t n, uint64_t seed,
+                  const int32_t* type, const double* pos, const double* dir, const double* ekin,
+                  const uint32_t* event, const uint64_t* tid, const uint32_t* nstep,
+                  double* pos_out, double* dir_out, double* ekin_out, double* edep_out,
+                  int32_t* vol_out, int32_t* vol_pre_out, int32_t* lim_out, int32_t* proc_out,
+                  int32_t* status_out, int32_t* nchild_out,
+                  int32_t* ch_type, double* ch_ekin, double* ch_dir, uint64_t* ch_tid,
+                  double* s_out, double* sphys_out, double* dbnd_out, double* safety_out, double* seloss_out);
+
 /* ---- unit-level access for the pin tests ---- */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double or_u53(uint32_t wa, uint32_t wb);

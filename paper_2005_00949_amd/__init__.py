@@ -25,6 +25,8 @@ DEPOSIT_FLOAT, DEPOSIT_FIXED = 0, 1
 FS_COMPTON, FS_PAIR, FS_BREMS, FS_MOLLER, FS_BHABHA = 0, 1, 2, 3, 4
 FS_ALL = 31
 DBG_STEP, DBG_PHILOX, DBG_COMPACT, DBG_TABLE, DBG_GEOM = 0, 1, 2, 3, 4
+# the step ended after one of its stages (Sec. 2.1.2)
+DBG_THRU_LIMIT, DBG_THRU_GEOM, DBG_THRU_MOVE, DBG_THRU_MSC, DBG_THRU_ELOSS = 5, 6, 7, 8, 9
 MAX_ELEM = 8
 PROC_NAMES = ["compton", "pair", "moller", "bhabha", "brems_em", "brems_ep", "annihilation", "null"]
 # table ids for DBG_TABLE: type * 4 + column, 12 = node energies
@@ -95,7 +97,7 @@ class DebugIO(C.Structure):
         ["type", "pos_in", "dir_in", "ekin_in", "event", "tid", "nstep", "vol_in", "words", "codes",
          "pos", "dir", "ekin", "edep", "vol", "vol_pre", "limiter", "process", "status", "n_children",
          "ch_type", "ch_ekin", "ch_dir", "ch_tid", "step", "s_phys", "d_bnd", "safety", "words_out",
-         "index", "counts", "values"]]
+         "index", "counts", "values", "s_eloss"]]
 
 
 TRACE_DTYPE = np.dtype([("tid", "<u8"), ("event", "<u4"), ("nstep", "<u4"), ("type", "<i4"),
@@ -277,7 +279,10 @@ class Engine:
     def _debug(self, stage, n, io):
         _check(self.lib.gv_debug_step(stage, n, C.byref(io)))
 
-    def debug_step(self, st, seed, precision=P64):
+    def debug_step(self, st, seed, precision=P64, stage=DBG_STEP):
+        """One step of each state (stage = DBG_STEP), or the step ended after
+        one of its stages (stage = DBG_THRU_LIMIT ... DBG_THRU_ELOSS, which
+        also return s_eloss)."""
         n = len(st["type"])
         f64 = lambda *s: np.zeros(s, dtype=np.float64)
         i32 = lambda *s: np.zeros(s, dtype=np.int32)
@@ -285,6 +290,8 @@ class Engine:
                  limiter=i32(n), process=i32(n), status=i32(n), n_children=i32(n), ch_type=i32(n, 2),
                  ch_ekin=f64(n, 2), ch_dir=f64(n, 2, 3), ch_tid=np.zeros((n, 2), np.uint64),
                  step=f64(n), s_phys=f64(n), d_bnd=f64(n), safety=f64(n))
+        if stage != DBG_STEP:
+            o["s_eloss"] = f64(n)
         keep = dict(type=np.ascontiguousarray(st["type"], np.int32),
                     pos_in=np.ascontiguousarray(st["pos"], np.float64),
                     dir_in=np.ascontiguousarray(st["dir"], np.float64),
@@ -302,7 +309,9 @@ class Engine:
         io.status, io.n_children, io.ch_type = _p(o["status"]), _p(o["n_children"]), _p(o["ch_type"])
         io.ch_ekin, io.ch_dir, io.ch_tid = _p(o["ch_ekin"]), _p(o["ch_dir"]), _p(o["ch_tid"])
         io.step, io.s_phys, io.d_bnd, io.safety = _p(o["step"]), _p(o["s_phys"]), _p(o["d_bnd"]), _p(o["safety"])
-        self._debug(DBG_STEP, n, io)
+        if stage != DBG_STEP:
+            io.s_eloss = _p(o["s_eloss"])
+        self._debug(stage, n, io)
         return o
 
     def debug_philox(self, words):

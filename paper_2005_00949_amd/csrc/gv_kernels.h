@@ -488,6 +488,8 @@ __global__ void k_dbg_geom(const double* pos, const double* dir, const int* vol_
 }
 
 struct DbgStepIO {
+    int stop;              // 0: the whole step; else the stage it ends after (kThru*)
+    double* s_eloss;       // continuous-loss length (stop > 0 only)
     const int* type;
     const double* pos_in;
     const double* dir_in;
@@ -534,7 +536,13 @@ __global__ void k_dbg_step(DbgStepIO io, long long n, uint64_t seed, TabView<typ
     t.nstep = io.nstep[i];
     t.vol = locate(c_geom, t.x);
     StepOut<R> o;
-    step_track<P, true>(c, t, o);
+    if (io.stop == 0) {
+        step_track<P, true>(c, t, o);
+    } else {
+        double s_eloss;
+        step_track_through(c, t, o, io.stop, s_eloss);
+        io.s_eloss[i] = s_eloss;
+    }
     for (int a = 0; a < 3; ++a) {
         io.pos[3 * i + a] = t.x[a];
         io.dir[3 * i + a] = (double)t.u[a];
@@ -634,23 +642,18 @@ struct Ctrl {
 
 // Work of an RK45 move before it is integrated (Sec. 3.6 sorts field
 // propagation work by length over radius of curvature): its turning angle at
-// the start, s |q kKB B x u| / p, in units of the turning the integrator
-// allows one attempt, i.e. the number of attempts it needs at least.  Parked
-// moves of more than kRkFirstTurns are integrated before the others (the
-// paper's pre-processed baskets), so the queue drains on single-attempt moves
-// instead of waiting for a long integration that started last.
+// the start, s / rcurv (rcurv = p / (kKB |B x u|), formed by the step's field
+// rule), in units of the turning the integrator allows one attempt, i.e. the
+// number of attempts it needs at least.  Parked moves of more than
+// kRkFirstTurns are integrated before the others (the paper's pre-processed
+// baskets), so the queue drains on single-attempt moves instead of waiting
+// for a long integration that started last.
 constexpr double kRkFirstTurns = 1.0;
 
-template <class P, class R = typename P::R>
-__device__ __forceinline__ double rk_turns(const Track<P>& t, double s)
+__device__ __forceinline__ double rk_turns(double s, double rcurv)
 {
-    R B[3];
-    field_at<R>(c_geom, t.x, B);
-    const R cx = t.u[1] * B[2] - t.u[2] * B[1], cy = t.u[2] * B[0] - t.u[0] * B[2], cz = t.u[0] * B[1] - t.u[1] * B[0];
-    const double bperp = sqrt((double)(cx * cx + cy * cy + cz * cz));
-    const double Td = (double)t.T;
     const double theta = 0.8 * sqrt(sqrt(c_phys.rk_tol / kDpK));
-    return s * kKB * bperp / (theta * sqrt(Td * (Td + 2.0 * kMe)));
+    return s / (theta * rcurv);
 }
 
 // A step parked at its RK45 move (the integration queue of the batched
@@ -869,7 +872,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                 Prop<R> pr;
                 iters += 1;
                 if (step_track_park(c, t, o, L, G, pr)) {
-                    if constexpr (TY != kGamma) park_job<P, TY>(A, t, L, G, pr, rk_turns<P>(t, pr.s));
+                    if constexpr (TY != kGamma) park_job<P, TY>(A, t, L, G, pr, rk_turns(pr.s, pr.rcurv));
                     o.status = kParked;
                     break;
                 }

@@ -1763,9 +1763,11 @@ int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
         for (int q = 0; q < 3; ++q) io->counts[q] = hc[q];
         return GV_OK;
     }
-    if (stage == GV_DBG_STEP) {
+    if (stage == GV_DBG_STEP || (stage >= GV_DBG_THRU_LIMIT && stage <= GV_DBG_THRU_ELOSS)) {
+        const int stop = stage == GV_DBG_STEP ? 0 : stage - GV_DBG_THRU_LIMIT + kThruLimit;
         if (!io->type || !io->pos_in || !io->dir_in || !io->ekin_in || !io->event || !io->tid || !io->nstep)
             return fail(GV_E_INVALID_ARG, "step inputs");
+        if (stop && !io->s_eloss) return fail(GV_E_INVALID_ARG, "step outputs: s_eloss");
         if (!io->pos || !io->dir || !io->ekin || !io->edep || !io->vol || !io->vol_pre || !io->limiter ||
             !io->process || !io->status || !io->n_children || !io->ch_type || !io->ch_ekin || !io->ch_dir ||
             !io->ch_tid || !io->step || !io->s_phys || !io->d_bnd || !io->safety)
@@ -1774,6 +1776,8 @@ int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
             if (io->type[i] < 0 || io->type[i] > 2 || !(io->ekin_in[i] > 0.0))
                 return fail(GV_E_INVALID_ARG, "step input type/energy");
         DbgStepIO d;
+        d.stop = stop;
+        d.s_eloss = stop ? (double*)dalloc(8 * n) : nullptr;
         d.type = (const int*)up(io->type, 4 * n);
         d.pos_in = (const double*)up(io->pos_in, 24 * n);
         d.dir_in = (const double*)up(io->dir_in, 24 * n);
@@ -1801,7 +1805,7 @@ int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
         d.safety = (double*)dalloc(8 * n);
         for (void* p : allocs)
             if (!p) return fail(GV_E_HIP, "allocation failed");
-        if (allocs.size() != 25) return fail(GV_E_HIP, "allocation failed");
+        if (allocs.size() != (stop ? 26u : 25u)) return fail(GV_E_HIP, "allocation failed");
         if (io->precision == GV_P64)
             k_dbg_step<P64><<<g, 128, 0, s>>>(d, n, io->seed, tab_view<double>());
         else
@@ -1825,6 +1829,7 @@ int gv_debug_step(int32_t stage, int64_t n, gv_debug_io* io)
         HIPCHK(hipMemcpyAsync(io->s_phys, d.s_phys, 8 * n, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(io->d_bnd, d.d_bnd, 8 * n, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(io->safety, d.safety, 8 * n, hipMemcpyDeviceToHost, s));
+        if (stop) HIPCHK(hipMemcpyAsync(io->s_eloss, d.s_eloss, 8 * n, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return GV_OK;
     }

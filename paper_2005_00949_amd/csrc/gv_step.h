@@ -82,6 +82,7 @@ template <class R> struct Prop {
     int lim;
     int crossed;
     RkTally rk;
+    double rcurv;   // radius of curvature at the pre-step point (charged tracks in a field)
 };
 
 template <class P> struct Ctx {
@@ -309,7 +310,10 @@ __device__ inline bool stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
     }
     if (pr.lim == kLimGeom) pr.s += c.ph->push;
     if (INTEG && c.ph->field_method != kFieldHelix) {
-        if (PARK && c.ph->field_method == kFieldRk45) return true;
+        if (PARK && c.ph->field_method == kFieldRk45) {
+            pr.rcurv = rcurv;
+            return true;
+        }
         double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
         const double T = (double)t.T;
         if (c.ph->field_method == kFieldRk45) {
@@ -583,6 +587,42 @@ __device__ inline void step_track(const Ctx<P>& c, Track<P>& t, StepOut<R>& o)
     Prop<R> pr;
     stage_move<P, INTEG, VAC>(c, t, L, G, pr);
     step_after_move(c, t, L, G, pr, o);
+}
+
+// The same step ended after one of its stages (Sec. 2.1.2), for the
+// per-stage test entry: s_phys and the continuous-loss length after
+// ComputeIntLen, then the boundary distance and safety, then the step length,
+// limiter and the moved track, then the deflection, then the loss.
+enum : int { kThruLimit = 1, kThruGeom = 2, kThruMove = 3, kThruMsc = 4, kThruEloss = 5 };
+
+template <class P, class R = typename P::R>
+__device__ inline void step_track_through(const Ctx<P>& c, Track<P>& t, StepOut<R>& o, int stop, double& s_eloss)
+{
+    init_out(t, o);
+    s_eloss = 0.0;
+    if (!stage_prestep(c, t, o)) return;
+    Limits<R> L;
+    stage_limit<P>(c, t, L);
+    o.s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
+    s_eloss = L.s_eloss >= big_len<R>() ? kInf : (double)L.s_eloss;
+    if (stop == kThruLimit) return;
+    Geo G;
+    stage_geom<P>(c, t, G);
+    o.d_bnd = G.d_bnd;
+    o.safety = G.safety;
+    if (stop == kThruGeom) return;
+    Prop<R> pr;
+    stage_move<P, true>(c, t, L, G, pr);
+    o.did_step = 1;
+    o.s = pr.s;
+    o.lim = pr.lim;
+    o.rk = pr.rk;
+    if (stop == kThruMove) return;
+    stage_msc(c, t, L, pr);
+    if (stop == kThruMsc) return;
+    const bool stopped = stage_eloss(c, t, L, pr, o);
+    if (stop == kThruEloss) return;
+    stage_finish(c, t, L, pr, stopped, o);
 }
 
 // The same step, stopped at an RK45 move (returns true: the track is unmoved

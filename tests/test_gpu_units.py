@@ -191,6 +191,44 @@ def test_single_step_mixed_parity(gv, oracle_mod, which):
     gvtest.assert_single_step_parity(flips, worst, margins, 1e-5, False)
 
 
+STAGES = ["limit", "geom", "move", "msc", "eloss"]
+
+
+@pytest.mark.parametrize("precision", ["p64", "pmix"])
+@pytest.mark.parametrize("stage", STAGES)
+def test_stage_parity(gv, oracle_mod, stage, precision):
+    """The step ended after each of its stages (Sec. 2.1.2: ComputeIntLen,
+    GeomQuery, Propagation, multiple scattering, continuous loss), through
+    the per-stage entry, against the oracle ended at the same stage: every
+    output produced so far, with the continuous-loss length, on 100,000
+    random states in the 4 T slab stack, at the single-step bar of each
+    precision (FP64: no flip; mixed: flips only within 10 tol of a decision)."""
+    geom = gv_inputs.slab_calorimeter(50, (0.0, 4.0, 0.0))
+    k = STAGES.index(stage)
+    p = gv.P64 if precision == "p64" else gv.PMIX
+    tol = 1e-12 if p == gv.P64 else 1e-5
+    orc = oracle_mod.Oracle(geom)
+    eng = _engine(gv, geom)
+    n = 100_000
+    st = gv_inputs.random_states(n, 40 + k, geom)
+    if p == gv.PMIX:
+        st["ekin"] = st["ekin"].astype(np.float32).astype(np.float64)
+        st["dir"] = st["dir"].astype(np.float32).astype(np.float64)
+    seed = 0x5A6E
+    ref = orc.single_step(st, seed, k + 1)
+    got = eng.debug_step(st, seed, precision=p, stage=gv.DBG_THRU_LIMIT + k)
+    flips, worst = gvtest.compare_steps(got, ref, st, tol)
+    margins = gvtest.flip_margins(got, ref, st, orc, geom, seed)
+    a, b = got["s_eloss"], ref["s_eloss"]
+    fin = b < 1e299
+    assert np.array_equal(a >= 1e299, ~fin)
+    se = np.abs(a[fin] - b[fin]) / np.maximum(np.abs(b[fin]), 1e-300)
+    print(f"\n[stage {stage} {precision}] flips {flips}/{n} (oracle margins {sorted(margins.values())}); "
+          f"s_eloss worst {float(se.max()) if se.size else 0.0:.2e}; worst {worst}")
+    assert (se <= tol).all()
+    gvtest.assert_single_step_parity(flips, worst, margins, tol, p == gv.P64)
+
+
 @pytest.mark.parametrize("precision", ["p64", "pmix"])
 def test_single_step_parity_table_sampling(gv, oracle_mod, precision):
     """One step with every final state drawn from the alias tables."""

@@ -571,3 +571,53 @@ def test_pair_and_brems_secondary_angles(oracle_mod):
     assert br.sum() > 1000
     assert np.all(r["ch_type"][br, 0] == GAMMA)
     assert np.all(r["ch_dir"][br, 0] == r["dir"][br])
+
+
+@pytest.mark.parametrize("which", ["slab0", "slab4T", "barrel"])
+def test_stage_prefixes_agree_with_the_whole_step(oracle_mod, which):
+    """The step ended after each stage (the per-stage reference of the GPU
+    stage tests) is the whole step's state at that point: ComputeIntLen
+    leaves the track unmoved and gives the whole step's s_phys, with the
+    continuous-loss length of the eloss pins (the whole range below 1 mm,
+    else 20 % of it but at least 1 mm, infinite for photons and vacuum);
+    GeomQuery adds the whole step's boundary distance and safety;
+    Propagation the whole step's length and limiter, and, for a photon or a
+    track in vacuum (no deflection or loss follows), its end state;
+    scattering the whole step's direction and the loss its energy and
+    deposit wherever no discrete interaction follows.  Catches an early exit
+    placed in the wrong stage or a stage that writes its output late."""
+    geom = {"slab0": gv_inputs.slab_calorimeter(50), "slab4T": gv_inputs.slab_calorimeter(50, (0.0, 4.0, 0.0)),
+            "barrel": gv_inputs.barrel()}[which]
+    o = oracle_mod.Oracle(geom)
+    st = gv_inputs.random_states(4000, 77, geom)
+    full = o.single_step(st, SEED)
+    alive = full["status"] == 0
+    r = o.single_step(st, SEED, oracle_mod.STOP_LIMIT)
+    walked = full["limiter"] >= 0
+    assert np.array_equal(r["pos"], st["pos"]) and np.array_equal(r["dir"], st["dir"])
+    assert np.array_equal(r["ekin"][walked], st["ekin"][walked])
+    assert np.array_equal(r["s_phys"], full["s_phys"]) and np.all(r["step"] == 0.0) and np.all(r["limiter"] == -1)
+    for i in np.where(walked)[0]:
+        typ, T = int(st["type"][i]), float(st["ekin"][i])
+        m = int(geom["material"][r["vol_pre"][i] - 1]) if r["vol_pre"][i] >= 1 else -1
+        if typ == GAMMA or m < 0:
+            assert r["s_eloss"][i] >= 1e299
+        else:
+            R = o.table_value(m, "R_em" if typ == ELECTRON else "R_ep", T)
+            assert r["s_eloss"][i] == (R if R <= 0.1 else max(0.2 * R, 0.1))
+    r = o.single_step(st, SEED, oracle_mod.STOP_GEOM)
+    assert np.array_equal(r["d_bnd"], full["d_bnd"]) and np.array_equal(r["safety"], full["safety"])
+    assert np.array_equal(r["pos"], st["pos"]) and np.all(r["step"] == 0.0)
+    r = o.single_step(st, SEED, oracle_mod.STOP_MOVE)
+    assert np.array_equal(r["step"], full["step"]) and np.array_equal(r["limiter"], full["limiter"])
+    vac = np.array([v < 1 or geom["material"][v - 1] < 0 for v in full["vol_pre"]])
+    same = walked & ((st["type"] == GAMMA) | vac) & (full["process"] < 0)
+    assert same.sum() > 100
+    assert np.array_equal(r["pos"][same], full["pos"][same]) and np.array_equal(r["dir"][same], full["dir"][same])
+    assert np.array_equal(r["vol"][walked], full["vol"][walked])
+    r = o.single_step(st, SEED, oracle_mod.STOP_MSC)
+    quiet = walked & (full["process"] < 0) & alive
+    assert np.array_equal(r["dir"][quiet], full["dir"][quiet]) and np.array_equal(r["pos"][quiet], full["pos"][quiet])
+    r = o.single_step(st, SEED, oracle_mod.STOP_ELOSS)
+    assert quiet.sum() > 1000
+    assert np.array_equal(r["ekin"][quiet], full["ekin"][quiet]) and np.array_equal(r["edep"][quiet], full["edep"][quiet])
