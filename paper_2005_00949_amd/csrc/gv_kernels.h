@@ -1094,6 +1094,30 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
     if (!__syncthreads_and(vac)) return;
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
     int calls = 0, kept = 0;
+    if (n1 + n2 <= (uint32_t)(kVacHelperBlock / 64)) {
+        // Few loopers (the usual end of a transport): one wavefront per
+        // looper, its state uniform across the wavefront, so that the step's
+        // tests compile to scalar branches instead of lane-mask updates (the
+        // arithmetic is the same).
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        if (w >= n1 + n2) return;
+        const int tw = w < n1 ? kElectron : kPositron;
+        const uint32_t sw = w < n1 ? w : w - n1;
+        Track<P> tu;
+        load_track(A.in[tw], sw, tw, tu);
+        const WorldRun<P> run = world_run(c, tu);
+        if (A.S.trace) helper_steps<P, true>(A, c, run, tu, max_steps, calls, kept);
+        else helper_steps<P, false>(A, c, run, tu, max_steps, calls, kept);
+        if ((threadIdx.x & 63) == 0) {
+            if (kept) {
+                store_track(A.in[tw], sw, tu);
+                atomicAdd(&A.S.counters[kCSteps + tw], (unsigned long long)kept);
+                atomicAdd(&A.S.counters[kCHelperSteps], (unsigned long long)kept);
+            }
+            if (calls) atomicAdd(&A.S.counters[kCLaneSlots], 64ull * (unsigned)calls);
+        }
+        return;
+    }
     if (active) {
         // vacuum keeps the kinetic energy: the run constants hold for every
         // kept step.  Without a trace the loop is its own copy, in which the
