@@ -119,17 +119,52 @@ def test_full_c4_fp64_plain_equals_batched(gv):
     (the vacuum forms of the step and the tail helper included) give
     bit-identical deposits, ledgers and step counts."""
     geom, prim, seed = gv_inputs.workload("c4")
-    out = {}
+    out, helper = {}, {}
     for drv in (gv.DRIVER_BATCHED, gv.DRIVER_PLAIN):
         eng = gv.Engine(geom, driver=drv, precision=gv.P64, deposit_mode=gv.DEPOSIT_FIXED)
         e = eng.transport(prim, seed)
         st = eng.stats()
         out[drv] = (e, eng.ledger(), st["steps"], st["tracks"], st["interactions"], st["escaped"], st["killed"])
+        helper[drv] = st["helper_steps"]
         eng.close()
     a, b = out[gv.DRIVER_BATCHED], out[gv.DRIVER_PLAIN]
     print(f"\n[c4 FP64 plain vs batched] steps {sum(a[2])} / {sum(b[2])}; cells differing "
-          f"{int((a[0] != b[0]).sum())}; ledger rows differing {int((a[1] != b[1]).any(1).sum())}")
+          f"{int((a[0] != b[0]).sum())}; ledger rows differing {int((a[1] != b[1]).any(1).sum())}; "
+          f"helper steps {helper[gv.DRIVER_BATCHED]}")
+    assert helper[gv.DRIVER_BATCHED] > 0   # the tail helper took part
     assert a[2] == b[2] and a[3] == b[3] and a[4] == b[4] and a[5] == b[5] and a[6] == b[6]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_many_loopers_in_the_tail_plain_equals_batched(gv):
+    """1,500 c4 events plus twelve low-energy electrons circling behind the
+    calorimeter, in FP64 with fixed-point scores: the tail ends with more
+    loopers than the helper's one-wavefront-per-looper form takes, so its
+    lane-per-looper form steps them; deposits, ledgers and step counts equal
+    the plain driver's bit for bit."""
+    geom, prim, seed = gv_inputs.workload("c4", 1500)
+    back = geom["bounds"][-1]
+    ME, KB = 0.51099895, 2.99792458
+    extra = np.zeros(12, dtype=gv_inputs.PRIMARY_DTYPE)
+    for k in range(12):
+        T = 0.12 + 0.02 * k
+        r = np.sqrt(T * (T + 2 * ME)) / (KB * 4.0)
+        extra[k]["pdg"], extra[k]["ekin"], extra[k]["event"] = 11, T, 1500 + k
+        extra[k]["pos"] = (-15.0 + 2.5 * k, -10.0 + 1.5 * k, back + 2 * r + 1e-4 * (k + 1))
+        extra[k]["dir"] = (1.0, 0.0, 0.0)
+    prim = np.concatenate([prim, extra])
+    out = {}
+    for drv in (gv.DRIVER_BATCHED, gv.DRIVER_PLAIN):
+        eng = gv.Engine(geom, driver=drv, precision=gv.P64, deposit_mode=gv.DEPOSIT_FIXED,
+                        max_steps_per_track=100_000)
+        e = eng.transport(prim, seed)
+        st = eng.stats()
+        out[drv] = (e, eng.ledger(), st["steps"], st["killed"], st["escaped"], st["helper_steps"])
+        eng.close()
+    a, b = out[gv.DRIVER_BATCHED], out[gv.DRIVER_PLAIN]
+    print(f"\n[c4 1500 + 12 loopers] steps {sum(a[2])}, killed {a[3]}, helper steps {a[5]}")
+    assert a[5] > 0 and a[3] >= 12
+    assert a[2] == b[2] and a[3] == b[3] and a[4] == b[4]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
