@@ -65,6 +65,18 @@ def measured_traffic(steps_per_launch, workload, knobs):
     return None
 
 
+def shower_roofline(res):
+    """Algorithmic bytes per second of the step kernel outside the tail
+    replays: the transport's algorithmic bytes less 108 B per tail step
+    (mixed-precision slot read and moving fields written; the tail's loopers
+    have no secondaries), over the kernel time outside the tail."""
+    t = (sum(res["kern_ms"]) - sum(res["tail_ms"])) * 1e-3
+    b = res["alg_bytes"] - 108.0 * res["tail_steps"]
+    if t <= 0.0:
+        return None
+    return {"achieved": b / t / 1e9, "frac": b / t / HBM_PEAK, "kernel_ms_per_transport": t * 1e3 / len(res["kern_ms"])}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -609,7 +621,10 @@ def main():
                                "k_vacuum_helper before it is part of the launch",
                      "avg_launch_us": avg_launch_s * 1e6, "alg_bytes_per_launch": bytes_per_launch,
                      "steps_per_launch": steps_per_launch, "launches": res["launches"],
-                     "kernel_source_sha1": kernel_source_hash()},
+                     "kernel_source_sha1": kernel_source_hash(),
+                     # the same bytes over the launches of the shower phase only
+                     # (the tail's looper steps, 108 B each, taken out)
+                     "shower_phase": shower_roofline(res)},
         "cpu_baseline": cpu,
     }
     line = json.dumps(out)

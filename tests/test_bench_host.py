@@ -65,3 +65,15 @@ def test_host_cpus_and_ungated_comparison():
     y = rng.gamma(4.0, 1.0, size=(200, 10))
     r = bench.paired_layers(y + rng.normal(0, 0.5, y.shape), y, gate=False)
     assert "pass_" not in r and r["three_sigma_rel_median_big_layers"] > 0 and r["events"] == 200
+
+
+def test_shower_roofline_takes_the_tail_out():
+    """Shower-phase bytes per second: all algorithmic bytes less 108 B per
+    tail step, over the kernel time outside the tail."""
+    import bench
+    res = dict(kern_ms=[300.0, 200.0], tail_ms=[200.0, 100.0], alg_bytes=1.0e12 + 108.0 * 1.0e6, tail_steps=1.0e6)
+    r = bench.shower_roofline(res)
+    assert abs(r["achieved"] - 1.0e12 / 0.2 / 1e9) < 1e-6
+    assert abs(r["frac"] - 1.0e12 / 0.2 / 8.0e12) < 1e-12
+    assert abs(r["kernel_ms_per_transport"] - 100.0) < 1e-9
+    assert bench.shower_roofline(dict(kern_ms=[1.0], tail_ms=[1.0], alg_bytes=1.0, tail_steps=0.0)) is None
