@@ -539,8 +539,9 @@ def main():
         copy_probe(args.copy_probe, 3)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); events shard "
-              f"across GPUs without communication, see the design notes", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the transport shards by event across "
+              f"GPUs with no communication inside the step loop, so N GPUs run N independent event ranges",
+              file=sys.stderr)
         sys.exit(2)
 
     res, plain, b64 = run_gpu(args)
