@@ -1053,25 +1053,48 @@ k_step_batched(BatchArgs<P> A)
 // material or population above one workgroup makes it return at once.
 constexpr int kVacHelperBlock = 256;
 
-template <class P, bool TRACE, class R = typename P::R>
+// The helper's step forms: the looper forms of the helix in a uniform field
+// (the world step and the vacuum step), the general step with the helix in a
+// field map, or the general step with the field integrators; each is the
+// function the step kernel runs for such a track.
+enum : int { kHelperLooper = 0, kHelperHelix = 1, kHelperInteg = 2 };
+
+template <class P, bool TRACE, int HM, class R = typename P::R>
 __device__ __forceinline__ void helper_steps(const BatchArgs<P>& A, const Ctx<P>& c, const WorldRun<P>& run,
-                                             Track<P>& t, int max_steps, int& calls, int& kept)
+                                             Track<P>& t, int max_steps, int& calls, int& kept, RkSum& rks)
 {
     for (; calls < max_steps;) {
         Track<P> tn = t;
         StepOut<R> o;
         const uint32_t ns = t.nstep;
-        if (t.vol == 0) step_world(c, run, tn, o);
-        else step_track<P, false, true>(c, tn, o);
+        if constexpr (HM == kHelperLooper) {
+            if (t.vol == 0) step_world(c, run, tn, o);
+            else step_track<P, false, true>(c, tn, o);
+        } else {
+            step_track<P, HM == kHelperInteg>(c, tn, o);
+        }
         calls += 1;
         if (o.status != kAlive) break;
         if (tn.vol != t.vol && vol_material(c_geom, tn.vol) >= 0) break;
         if (TRACE && o.did_step) trace_step(A.S, tn, o.vol_pre, tn, o, ns);
+        if constexpr (HM == kHelperInteg) {
+            rks.acc += (uint32_t)o.rk.acc;
+            rks.rej += (uint32_t)o.rk.rej;
+            rks.slots += (uint32_t)o.rk.iters;
+        }
         t = tn;
         kept += 1;
     }
 }
-template <class P>
+
+// integration work of the helper's kept steps (RK4 / RK45), into the run counters
+__device__ __forceinline__ void helper_rk_counts(const Sinks& S, const RkSum& rks)
+{
+    if (rks.acc) atomicAdd(&S.counters[kCRkSub], (unsigned long long)rks.acc);
+    if (rks.rej) atomicAdd(&S.counters[kCRkRej], (unsigned long long)rks.rej);
+    if (rks.slots) atomicAdd(&S.counters[kCRkSlots], (unsigned long long)rks.slots);
+}
+template <class P, int HM>
 __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> A, int max_steps)
 {
     using R = typename P::R;
@@ -1106,9 +1129,12 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
         Track<P> tu;
         load_track(A.in[tw], sw, tw, tu);
         const WorldRun<P> run = world_run(c, tu);
-        if (A.S.trace) helper_steps<P, true>(A, c, run, tu, max_steps, calls, kept);
-        else helper_steps<P, false>(A, c, run, tu, max_steps, calls, kept);
+        RkSum rks{0u, 0u, 0u};
+        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, tu, max_steps, calls, kept, rks);
+        else helper_steps<P, false, HM>(A, c, run, tu, max_steps, calls, kept, rks);
         if ((threadIdx.x & 63) == 0) {
+            // (one looper per wavefront: its integration counts once, as one lane's)
+            helper_rk_counts(A.S, rks);
             if (kept) {
                 store_track(A.in[tw], sw, tu);
                 atomicAdd(&A.S.counters[kCSteps + tw], (unsigned long long)kept);
@@ -1123,8 +1149,10 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
         // kept step.  Without a trace the loop is its own copy, in which the
         // step records' other fields are dead.
         const WorldRun<P> run = world_run(c, t);
-        if (A.S.trace) helper_steps<P, true>(A, c, run, t, max_steps, calls, kept);
-        else helper_steps<P, false>(A, c, run, t, max_steps, calls, kept);
+        RkSum rks{0u, 0u, 0u};
+        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, t, max_steps, calls, kept, rks);
+        else helper_steps<P, false, HM>(A, c, run, t, max_steps, calls, kept, rks);
+        helper_rk_counts(A.S, rks);
         if (kept) {
             store_track(A.in[ty], slot, t);
             atomicAdd(&A.S.counters[kCSteps + ty], (unsigned long long)kept);

@@ -796,7 +796,14 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
     const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
     const bool rkq = rk_queue_mode();
     for (int k = 0; k < K; ++k) {
-        if (helper) k_vacuum_helper<P><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
+        if (helper) {
+            if (L.cfg.field_method != GV_FIELD_HELIX)
+                k_vacuum_helper<P, kHelperInteg><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
+            else if (L.geom.field_map == kMapUniform)
+                k_vacuum_helper<P, kHelperLooper><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
+            else
+                k_vacuum_helper<P, kHelperHelix><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
+        }
         if (rkq) launch_rk_queue_step<P>(tu.block, A[k & 1], grid, s);
         else launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
     }
@@ -811,8 +818,9 @@ template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
     drop_graph();
     int rc = capture<P>(tu, tu.occupancy * L.n_cu, tu.K, tu.inner_bulk, tu.inner_tail, false, &L.graph, &L.gexec);
     if (rc) return rc;
-    // the vacuum helper serves the helix in a uniform field (its step form)
-    const bool helper = L.cfg.field_method == GV_FIELD_HELIX && L.geom.field_map == kMapUniform;
+    // the vacuum helper steps the last loopers of the tail replays (with the
+    // looper forms of the helix in a uniform field, else the general step)
+    const bool helper = true;
     rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, helper, &L.graph_tail, &L.gexec_tail);
     if (rc) return rc;
     L.gkey = key;
