@@ -631,9 +631,12 @@ struct Ctrl {
     uint32_t halt;          // overflow as seen at the end of the previous launch
     uint32_t pad;
     uint64_t seed;          // run seed (device-resident so captured graphs are reusable)
-    uint32_t rk_count[2];   // integration queue: moves parked in this launch, per charged type
-    uint32_t rk_heavy[2];   // ... of which long (above kRkFirstTurns), listed first in the integration order
-    uint32_t rk_light[2];   // ... and short, listed after them
+    // integration queue, on a cache line of its own (every wavefront that
+    // parks a move adds to it): moves parked in this launch per charged type,
+    // long ones (above kRkFirstTurns, listed first in the integration order)
+    // in the low 32 bits, short ones (listed after them) in the high 32 bits,
+    // so that one atomic reserves a wavefront's job slots and order entries
+    alignas(128) unsigned long long rk_split[2];
     uint32_t rk_grab;       // next parked move for the integration kernel
     uint32_t rk_ticket;     // next chunk of parked moves for the resume kernel
     uint32_t rk_done;       // resume workgroups finished in this launch
@@ -687,7 +690,15 @@ template <class P> struct BatchArgs {
     RkJob<P>* jobs[2];       // integration queue per charged type (RK45 with arrival order)
     uint32_t* order[2];      // integration order per type: long moves from the front, short ones from the back
     uint32_t jcap;           // capacity per type of both
+    int regime;              // which populations this step kernel launch takes (kRunAlways, ...)
 };
+
+// A launch of the integration queue's bulk graph holds two step kernels: the
+// one that integrates inside the step takes a population below the tail
+// threshold, the park-only one a population at or above it; the other returns
+// before it touches anything.  (The first to run empties the input counts, so
+// the second then sees no population and returns too.)
+enum : int { kRunAlways = 0, kRunBelowTail = 1, kRunFromTail = 2 };
 
 // Primary ingest (the event server of Sec. 2.1): validated, typed primaries
 // with their track id (order within the event) are located in the geometry,
@@ -775,13 +786,22 @@ __device__ __forceinline__ void park_job(const BatchArgs<P>& A, const Track<P>& 
 {
     static_assert(TY == kElectron || TY == kPositron, "only charged steps are parked");
     constexpr int q = TY - 1;
-    const uint64_t pm = __ballot(1);
+    const bool heavy = turns > kRkFirstTurns;
+    const uint64_t pm = __ballot(1), hm = __ballot(heavy), lm = pm & ~hm;
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((unsigned long long)pm) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&A.ctrl->rk_count[q], (uint32_t)__popcll(pm));
-    base = (uint32_t)__shfl((int)base, leader, 64);
-    const uint32_t k = base + (uint32_t)__popcll(pm & ((1ull << lane) - 1ull));
+    unsigned long long old = 0ull;
+    if (lane == leader)
+        old = atomicAdd(&A.ctrl->rk_split[q],
+                        (unsigned long long)__popcll(hm) | ((unsigned long long)__popcll(lm) << 32));
+    const uint32_t hb = (uint32_t)__shfl((int)(uint32_t)old, leader, 64);
+    const uint32_t lb = (uint32_t)__shfl((int)(uint32_t)(old >> 32), leader, 64);
+    const uint64_t below = (1ull << lane) - 1ull;
+    // job slot in arrival order; integration order: the long moves are listed
+    // from the front of the order array, the short ones from its back.  Both
+    // order indices are at most k, so every store is in bounds; the regions
+    // never meet unless the launch overflows (and is then discarded).
+    const uint32_t k = hb + lb + (uint32_t)__popcll(pm & below);
     if (k < A.jcap) {
         RkJob<P>& J = A.jobs[q][k];
         J.t = t;
@@ -789,25 +809,24 @@ __device__ __forceinline__ void park_job(const BatchArgs<P>& A, const Track<P>& 
         J.G = G;
         J.s = pr.s;
         J.lim = pr.lim;
+        if (heavy) A.order[q][hb + (uint32_t)__popcll(hm & below)] = k;
+        else A.order[q][A.jcap - 1u - (lb + (uint32_t)__popcll(lm & below))] = k;
     } else {
         atomicOr(&A.ctrl->overflow, 1u);
     }
-    // integration order: the longest moves are listed from the front of the
-    // order array, the others from its back (the two never meet: every stored
-    // move is listed once and at most jcap are stored)
-    const bool stored = k < A.jcap;
-    const bool heavy = stored && turns > kRkFirstTurns;
-    const uint64_t hm = __ballot(heavy), lm = __ballot(stored && !heavy);
-    uint32_t hb = 0, lb = 0;
-    if (lane == leader) {
-        if (hm) hb = atomicAdd(&A.ctrl->rk_heavy[q], (uint32_t)__popcll(hm));
-        if (lm) lb = atomicAdd(&A.ctrl->rk_light[q], (uint32_t)__popcll(lm));
-    }
-    hb = (uint32_t)__shfl((int)hb, leader, 64);
-    lb = (uint32_t)__shfl((int)lb, leader, 64);
-    const uint64_t below = (1ull << lane) - 1ull;
-    if (heavy) A.order[q][hb + (uint32_t)__popcll(hm & below)] = k;
-    else if (stored) A.order[q][A.jcap - 1u - (lb + (uint32_t)__popcll(lm & below))] = k;
+}
+
+// parked moves of one type and how many of them are long; none if the
+// integration queue overflowed in this launch (the launch is then discarded)
+struct RkCounts {
+    uint32_t n, heavy;
+};
+__device__ __forceinline__ RkCounts rk_counts(const Ctrl* ctrl, int q, uint32_t jcap, bool halt)
+{
+    const unsigned long long v = ctrl->rk_split[q];
+    const unsigned long long h = v & 0xffffffffull, l = v >> 32;
+    if (halt || h + l > jcap) return RkCounts{0u, 0u};
+    return RkCounts{(uint32_t)(h + l), (uint32_t)h};
 }
 
 template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, bool PARK = false, class R = typename P::R>
@@ -815,7 +834,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
                                               uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks,
-                                              unsigned long long* lane_slots_lds, bool vac_ok, bool park)
+                                              unsigned long long* lane_slots_lds, bool vac_ok)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -835,7 +854,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         for (; iters < inner;) {
             uint32_t ns = t.nstep;
             const bool acc_empty = (acc.e == 0.0) & (acc.x == 0ull);
-            if (TY != kGamma && !INTEG && vac_ok && __all((t.vol == 0) & acc_empty)) {
+            if (TY != kGamma && !INTEG && !PARK && vac_ok && __all((t.vol == 0) & acc_empty)) {
                 // A wavefront whose charged tracks are all in volumes without
                 // material (the loopers of a transport's low-population tail)
                 // steps them in the vacuum form of the step, here in the world
@@ -855,7 +874,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                     if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
                     ns = t.nstep;
                 }
-            } else if (TY != kGamma && !INTEG && vac_ok &&
+            } else if (TY != kGamma && !INTEG && !PARK && vac_ok &&
                        __all((vol_material(c_geom, t.vol) < 0) & acc_empty)) {
                 for (;;) {
                     step_track<P, false, true>(c, t, o);
@@ -866,7 +885,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                     if (A.S.trace && o.did_step) trace_step(A.S, t, o.vol_pre, t, o, ns);
                     ns = t.nstep;
                 }
-            } else if (PARK && TY != kGamma && park) {
+            } else if (PARK && TY != kGamma) {
                 Limits<R> L;
                 Geo G;
                 Prop<R> pr;
@@ -957,7 +976,9 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
 }
 
 // INTEG: field integrators compiled in (field_method RK4 / RK45); the helix
-// variant leaves them out and keeps its register budget.  The mixed-precision
+// variant leaves them out and keeps its register budget.  PARK (without
+// INTEG): the integration queue's step kernel, which parks every charged move
+// in a field and so has the helix variant's register budget.  The mixed-precision
 // helix variant is held to three wavefronts per SIMD (168 VGPRs): the step
 // chain is latency-bound, and a third resident wavefront hides more of it.
 template <class P, int BLOCK, bool STABLE, bool INTEG, bool PARK = false>
@@ -968,9 +989,6 @@ k_step_batched(BatchArgs<P> A)
     __shared__ unsigned cnt_lds[kNCount];
     __shared__ unsigned long long rk_lds[4];
     __shared__ DepCache dc;
-    for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
-    if (threadIdx.x < 4) rk_lds[threadIdx.x] = 0ull;
-    dep_clear<BLOCK>(dc);
 
     const int pin = A.parity;
     // after an overflow (reported to the host, which reruns the window) the
@@ -989,12 +1007,16 @@ k_step_batched(BatchArgs<P> A)
     // the integration queue pays off while the population fills the GPU; in
     // the low-population tail each lane integrates its own track (inner_tail
     // steps per launch instead of one parked step per launch)
-    const bool park = PARK && population >= A.tail_threshold;
+    if (A.regime == kRunBelowTail && population >= A.tail_threshold) return;
+    if (A.regime == kRunFromTail && population < A.tail_threshold) return;
     // only as many workgroups as there are baskets take part; the rest leave
     // at once, so a small population costs a small launch
     const uint32_t baskets = (n_chunks + (uint32_t)A.basket_chunks - 1) / (uint32_t)A.basket_chunks;
     const uint32_t participants = baskets < gridDim.x ? (baskets > 0 ? baskets : 1u) : gridDim.x;
     if (blockIdx.x >= participants) return;
+    for (int i = threadIdx.x; i < kNCount; i += BLOCK) cnt_lds[i] = 0;
+    if (threadIdx.x < 4) rk_lds[threadIdx.x] = 0ull;
+    dep_clear<BLOCK>(dc);
     Ctx<P> c{A.ctrl->seed, &c_geom, &c_phys, A.tv};
     const bool vac_ok = c_geom.field_map == kMapUniform;
     uint32_t steps_g = 0, steps_e = 0, steps_p = 0;
@@ -1013,15 +1035,15 @@ k_step_batched(BatchArgs<P> A)
             if (chunk < c0)
                 process_chunk<P, kGamma, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc,
                                                                      cnt_lds, steps_g, loads, stores, n_chunks, rks,
-                                                                     &rk_lds[3], vac_ok, park);
+                                                                     &rk_lds[3], vac_ok);
             else if (chunk < c0 + c1)
                 process_chunk<P, kElectron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner,
                                                                         sh, dc, cnt_lds, steps_e, loads, stores, n_chunks,
-                                                                        rks, &rk_lds[3], vac_ok, park);
+                                                                        rks, &rk_lds[3], vac_ok);
             else
                 process_chunk<P, kPositron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch,
                                                                         inner, sh, dc, cnt_lds, steps_p, loads, stores,
-                                                                        n_chunks, rks, &rk_lds[3], vac_ok, park);
+                                                                        n_chunks, rks, &rk_lds[3], vac_ok);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);
@@ -1097,7 +1119,6 @@ __device__ __forceinline__ void helper_rk_counts(const Sinks& S, const RkSum& rk
 template <class P, int HM>
 __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> A, int max_steps)
 {
-    using R = typename P::R;
     if (A.ctrl->halt != 0) return;
     const int pin = A.parity;
     const uint32_t n0 = min(A.ctrl->count[pin][kGamma], A.cap);
@@ -1119,9 +1140,9 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
     int calls = 0, kept = 0;
     if (n1 + n2 <= (uint32_t)(kVacHelperBlock / 64)) {
         // Few loopers (the usual end of a transport): one wavefront per
-        // looper, its state uniform across the wavefront, so that the step's
-        // tests compile to scalar branches instead of lane-mask updates (the
-        // arithmetic is the same).
+        // looper, so that loopers step side by side on separate SIMDs
+        // instead of taking turns in the divergent branches of one wavefront
+        // (the arithmetic is the same).
         const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         if (w >= n1 + n2) return;
         const int tw = w < n1 ? kElectron : kPositron;
@@ -1181,16 +1202,15 @@ constexpr int kRkBlock = 256;
 template <class P>
 __global__ void __launch_bounds__(kRkBlock) k_rk_integrate(BatchArgs<P> A)
 {
-    using R = typename P::R;
     __shared__ unsigned long long slots_lds;
     if (threadIdx.x == 0) slots_lds = 0ull;
     __syncthreads();
     const bool halt = A.ctrl->halt != 0;
-    const uint32_t ne = halt ? 0u : min(A.ctrl->rk_count[0], A.jcap);
-    const uint32_t np = halt ? 0u : min(A.ctrl->rk_count[1], A.jcap);
+    const RkCounts re = rk_counts(A.ctrl, 0, A.jcap, halt), rp = rk_counts(A.ctrl, 1, A.jcap, halt);
+    const uint32_t ne = re.n, np = rp.n;
     const uint32_t total = ne + np;
     // integration order: long moves of both types, then short ones
-    const uint32_t he = halt ? 0u : min(A.ctrl->rk_heavy[0], ne), hp = halt ? 0u : min(A.ctrl->rk_heavy[1], np);
+    const uint32_t he = re.heavy, hp = rp.heavy;
     const uint32_t le = ne - he;
     const double tol = c_phys.rk_tol;
     const int max_sub = c_phys.rk_max_sub;
@@ -1342,8 +1362,8 @@ __global__ void __launch_bounds__(BLOCK) k_rk_resume(BatchArgs<P> A)
     if (threadIdx.x < 2) rk_lds[threadIdx.x] = 0ull;
     dep_clear<BLOCK>(dc);
     const bool halt = A.ctrl->halt != 0;
-    const uint32_t ne = halt ? 0u : min(A.ctrl->rk_count[0], A.jcap);
-    const uint32_t np = halt ? 0u : min(A.ctrl->rk_count[1], A.jcap);
+    const uint32_t ne = rk_counts(A.ctrl, 0, A.jcap, halt).n;
+    const uint32_t np = rk_counts(A.ctrl, 1, A.jcap, halt).n;
     const uint32_t ce = (ne + BLOCK - 1) / BLOCK, cp = (np + BLOCK - 1) / BLOCK;
     const uint32_t n_chunks = ce + cp;
     const uint32_t participants = n_chunks < gridDim.x ? (n_chunks > 0 ? n_chunks : 1u) : gridDim.x;
@@ -1381,10 +1401,8 @@ __global__ void __launch_bounds__(BLOCK) k_rk_resume(BatchArgs<P> A)
         const uint32_t d = atomicAdd(&A.ctrl->rk_done, 1u);
         if (d == participants - 1) {
             __threadfence();
-            A.ctrl->rk_count[0] = 0;
-            A.ctrl->rk_count[1] = 0;
-            A.ctrl->rk_heavy[0] = A.ctrl->rk_heavy[1] = 0;
-            A.ctrl->rk_light[0] = A.ctrl->rk_light[1] = 0;
+            A.ctrl->rk_split[0] = 0ull;
+            A.ctrl->rk_split[1] = 0ull;
             A.ctrl->rk_grab = 0;
             A.ctrl->rk_ticket = 0;
             A.ctrl->rk_done = 0;

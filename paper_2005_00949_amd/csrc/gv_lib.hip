@@ -627,8 +627,7 @@ int upload_ctrl(const uint32_t counts[3], uint64_t seed)
         c.count[1][t] = 0;
     }
     c.count[0][3] = c.count[1][3] = 0;
-    c.rk_count[0] = c.rk_count[1] = 0;
-    c.rk_heavy[0] = c.rk_heavy[1] = c.rk_light[0] = c.rk_light[1] = 0;
+    c.rk_split[0] = c.rk_split[1] = 0ull;
     c.rk_grab = c.rk_ticket = c.rk_done = 0;
     c.ticket = 0;
     c.overflow = 0;
@@ -717,24 +716,31 @@ bool rk_queue_mode()
            L.cfg.queue_order == GV_ORDER_ARRIVAL;
 }
 
-template <class P> void launch_rk_queue_step(int block, const BatchArgs<P>& A, int grid, hipStream_t s)
+// One launch of the integration queue's bulk graph: the step kernel that
+// integrates inside the step (taking populations below the tail threshold),
+// the park-only step kernel (taking the others), the integration kernel and
+// the resume kernel.  The tail graph integrates inside the step only.
+template <class P, int BLOCK> void launch_rk_queue_block(const BatchArgs<P>& A, int grid, hipStream_t s, bool tail)
+{
+    if (tail) {
+        k_step_batched<P, BLOCK, false, true><<<grid, BLOCK, 0, s>>>(A);
+        return;
+    }
+    BatchArgs<P> a = A;
+    a.regime = kRunBelowTail;
+    k_step_batched<P, BLOCK, false, true><<<grid, BLOCK, 0, s>>>(a);
+    a.regime = kRunFromTail;
+    k_step_batched<P, BLOCK, false, false, true><<<grid, BLOCK, 0, s>>>(a);
+    k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
+    k_rk_resume<P, BLOCK><<<grid, BLOCK, 0, s>>>(A);
+}
+
+template <class P> void launch_rk_queue_step(int block, const BatchArgs<P>& A, int grid, hipStream_t s, bool tail)
 {
     switch (block) {
-    case 64:
-        k_step_batched<P, 64, false, true, true><<<grid, 64, 0, s>>>(A);
-        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
-        k_rk_resume<P, 64><<<grid, 64, 0, s>>>(A);
-        break;
-    case 128:
-        k_step_batched<P, 128, false, true, true><<<grid, 128, 0, s>>>(A);
-        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
-        k_rk_resume<P, 128><<<grid, 128, 0, s>>>(A);
-        break;
-    default:
-        k_step_batched<P, 256, false, true, true><<<grid, 256, 0, s>>>(A);
-        k_rk_integrate<P><<<L.n_cu * 4, kRkBlock, 0, s>>>(A);
-        k_rk_resume<P, 256><<<grid, 256, 0, s>>>(A);
-        break;
+    case 64: launch_rk_queue_block<P, 64>(A, grid, s, tail); break;
+    case 128: launch_rk_queue_block<P, 128>(A, grid, s, tail); break;
+    default: launch_rk_queue_block<P, 256>(A, grid, s, tail); break;
     }
 }
 
@@ -758,12 +764,14 @@ template <class P> QueueMem<P>& batch_queues();
 template <> QueueMem<P64>& batch_queues<P64>() { return L.q64; }
 template <> QueueMem<PMix>& batch_queues<PMix>() { return L.qmix; }
 
-// capture K launches alternating parity (K even: a replay ends where it began)
+// capture K launches alternating parity (K even: a replay ends where it began);
+// tail: the tail graph, with the vacuum helper before each step launch and,
+// for RK45 with arrival order, integration inside the step only
 // vacuum steps per track and helper launch in the tail replays
 constexpr int kVacHelperSteps = 4096;
 
 template <class P>
-int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, bool helper, hipGraph_t* g,
+int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, bool tail, hipGraph_t* g,
             hipGraphExec_t* ge)
 {
     QueueMem<P>& Q = batch_queues<P>();
@@ -791,12 +799,13 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
         A[par].order[0] = order;
         A[par].order[1] = order ? order + L.rk_jcap : nullptr;
         A[par].jcap = jobs ? L.rk_jcap : 0u;
+        A[par].regime = kRunAlways;
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
     const bool rkq = rk_queue_mode();
     for (int k = 0; k < K; ++k) {
-        if (helper) {
+        if (tail) {
             if (L.cfg.field_method != GV_FIELD_HELIX)
                 k_vacuum_helper<P, kHelperInteg><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
             else if (L.geom.field_map == kMapUniform)
@@ -804,7 +813,7 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
             else
                 k_vacuum_helper<P, kHelperHelix><<<1, kVacHelperBlock, 0, s>>>(A[k & 1], kVacHelperSteps);
         }
-        if (rkq) launch_rk_queue_step<P>(tu.block, A[k & 1], grid, s);
+        if (rkq) launch_rk_queue_step<P>(tu.block, A[k & 1], grid, s, tail);
         else launch_step_dispatch<P>(tu.block, A[k & 1], grid, stable, s);
     }
     hipError_t ce = hipStreamEndCapture(s, g);
@@ -820,8 +829,7 @@ template <class P> int build_graph(const Tuning& tu, const GraphKey& key)
     if (rc) return rc;
     // the vacuum helper steps the last loopers of the tail replays (with the
     // looper forms of the helix in a uniform field, else the general step)
-    const bool helper = true;
-    rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, helper, &L.graph_tail, &L.gexec_tail);
+    rc = capture<P>(tu, tu.tail_grid, tu.tail_K, tu.inner_tail, tu.inner_tail, true, &L.graph_tail, &L.gexec_tail);
     if (rc) return rc;
     L.gkey = key;
     return GV_OK;

@@ -239,14 +239,16 @@ __device__ inline void stage_geom(const Ctx<P>& c, const Track<P>& t, Geo& G)
 // HELIX); INTEG = true adds the RK4 and RK45 integrators, which run in double
 // in both precision policies.  VAC (a volume without material in a uniform
 // field) leaves out the field-map evaluation.
-// PARK: an RK45 move is not integrated here; the function returns true with
-// the step's length and nominal limiter in pr and the track unmoved, and
-// stage_move_resume finishes the move from the integrated end point (the
-// batched driver's integration queue).
+// PARK (the batched driver's integration queue, field method RK45; no
+// integrator is compiled in): a charged move in a field is not made here; the
+// function returns true with the step's length, nominal limiter and radius of
+// curvature in pr and the track unmoved, and stage_move_resume finishes the
+// move from the integrated end point.
 template <class P, bool INTEG, bool VAC = false, bool PARK = false, class R = typename P::R>
 __device__ inline bool stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>& L, const Geo& G, Prop<R>& pr)
 {
 #pragma clang fp contract(off)
+    static_assert(!(PARK && INTEG), "a parked move is integrated by the integration queue");
     const DevGeom& g = *c.g;
     const double s_phys = L.s_phys >= big_len<R>() ? kInf : (double)L.s_phys;
     const double s_eloss = L.s_eloss >= big_len<R>() ? kInf : (double)L.s_eloss;
@@ -309,11 +311,11 @@ __device__ inline bool stage_move(const Ctx<P>& c, Track<P>& t, const Limits<R>&
         pr.lim = kLimField;
     }
     if (pr.lim == kLimGeom) pr.s += c.ph->push;
+    if constexpr (PARK) {
+        pr.rcurv = rcurv;
+        return true;
+    }
     if (INTEG && c.ph->field_method != kFieldHelix) {
-        if (PARK && c.ph->field_method == kFieldRk45) {
-            pr.rcurv = rcurv;
-            return true;
-        }
         double ud[3] = {(double)t.u[0], (double)t.u[1], (double)t.u[2]};
         const double T = (double)t.T;
         if (c.ph->field_method == kFieldRk45) {
@@ -635,7 +637,7 @@ __device__ inline bool step_track_park(const Ctx<P>& c, Track<P>& t, StepOut<R>&
     if (!stage_prestep(c, t, o)) return false;
     stage_limit<P>(c, t, L);
     stage_geom<P>(c, t, G);
-    if (stage_move<P, true, false, true>(c, t, L, G, pr)) return true;
+    if (stage_move<P, false, false, true>(c, t, L, G, pr)) return true;
     step_after_move(c, t, L, G, pr, o);
     return false;
 }
