@@ -369,7 +369,7 @@ def run_field_map(args, gv, torch, cfg):
                             ("rk45_in_step", gv.FIELD_RK45, gv.ORDER_STABLE)):
         eng.configure(field_method=fm, queue_order=order)
         eng.transport_staged(seed, edep.data_ptr())
-        ts, steps, sub, rej, slots, charged, kms = [], 0, 0, 0, 0, 0, 0.0
+        ts, steps, sub, rej, slots, charged, kms, parked = [], 0, 0, 0, 0, 0, 0.0, 0
         reps = 3 if fm == gv.FIELD_HELIX else 2
         for k in range(reps):
             torch.cuda.synchronize()
@@ -383,6 +383,7 @@ def run_field_map(args, gv, torch, cfg):
             sub += st["rk_substeps"]
             rej += st["rk_rejected"]
             slots += st["rk_lane_slots"]
+            parked += st["rk_parked"]
             kms += st["kernel_ms"]
         leg = dict(steps_per_s=steps / sum(ts), ms_per_transport=float(np.median(ts)) * 1e3,
                    kernel_ms_per_transport=kms / reps, e_dep_GeV=float(st["e_dep"]) * 1e-3 / len(prim),
@@ -398,7 +399,8 @@ def run_field_map(args, gv, torch, cfg):
             leg["integration"] = "each lane integrates its own track inside the step (stable-order queues)"
         if fm == gv.FIELD_RK45:
             leg.update(substeps_per_charged_step=sub / max(charged, 1), rejected_per_charged_step=rej / max(charged, 1),
-                       substeps_per_s=sub / sum(ts), idle_lane_fraction=1.0 - (sub + rej) / max(slots, 1))
+                       substeps_per_s=sub / sum(ts), idle_lane_fraction=1.0 - (sub + rej) / max(slots, 1),
+                       parked_fraction=parked / max(charged, 1))
         out[name] = leg
         log(f"[bench] field map {name}: {leg['steps_per_s']:.3g} steps/s, {leg['ms_per_transport']:.1f} ms"
             + (f", {leg['substeps_per_charged_step']:.2f} substeps + {leg['rejected_per_charged_step']:.2f} "

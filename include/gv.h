@@ -223,8 +223,10 @@ typedef struct {
                                        the autotuner, 0: defaults or caller's values */
     int32_t queue_order;
     int32_t reserved;
-    double tail_kernel_ms;          /* part of kernel_ms spent after the population peaked and
-                                       fell below the tail threshold (batched driver) */
+    double tail_kernel_ms;          /* part of kernel_ms spent in the tail replays (batched
+                                       driver): after the population peaked and fell below the
+                                       tail threshold, or, in a window whose population never
+                                       reaches the threshold, once a replay no longer raised it */
     int64_t rk_substeps;            /* RK45: accepted substeps */
     int64_t rk_rejected;            /* RK45: rejected attempts */
     int64_t rk_lane_slots;          /* RK45: 64 x the attempt rounds of every wavefront that
@@ -239,6 +241,9 @@ typedef struct {
                                        the lane use of the stepping loop (0 for the plain driver) */
     int64_t tail_steps;             /* steps taken in the launches counted in tail_kernel_ms */
     int64_t helper_steps;           /* of those, steps taken by the tail's vacuum helper kernel */
+    int64_t rk_parked;              /* RK45 with arrival order: charged steps parked at their move
+                                       in the integration queue (Sec. 3.6: lanes refilled as
+                                       integrations finish); the rest integrate inside the step */
 } gv_stats_t;
 
 /* Step-record layout written when trace_cap > 0 (112 bytes). */

@@ -87,7 +87,7 @@ class Stats(C.Structure):
                 ("tail_kernel_ms", C.c_double),
                 ("rk_substeps", C.c_int64), ("rk_rejected", C.c_int64), ("rk_lane_slots", C.c_int64),
                 ("lane_slots", C.c_int64), ("tail_steps", C.c_int64),
-                ("helper_steps", C.c_int64)]
+                ("helper_steps", C.c_int64), ("rk_parked", C.c_int64)]
 
 
 class DebugIO(C.Structure):

@@ -85,7 +85,7 @@ __device__ __forceinline__ void store_child(const Soa<P>& q, size_t i, const Tra
 // global counters (gv_stats)
 enum : int { kCSteps = 0, kCTracks = 3, kCProc = 6, kCEscaped = 14, kCKilled = 15, kCRej = 16, kCLoads = 17,
              kCStores = 18, kCRkSub = 19, kCRkRej = 20, kCRkSlots = 21, kCLaneSlots = 22, kCHelperSteps = 23,
-             kNCount = 24 };
+             kCRkParked = 24, kNCount = 25 };
 
 // per-lane sums of the adaptive-integration tallies over one launch
 struct RkSum {
@@ -892,6 +892,7 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
                 iters += 1;
                 if (step_track_park(c, t, o, L, G, pr)) {
                     if constexpr (TY != kGamma) park_job<P, TY>(A, t, L, G, pr, rk_turns(pr.s, pr.rcurv));
+                    atomicAdd(&cnt_lds[kCRkParked], 1u);
                     o.status = kParked;
                     break;
                 }
@@ -1066,7 +1067,8 @@ k_step_batched(BatchArgs<P> A)
 // Low-population helper of the tail replays.  When every track left is a
 // charged track in a volume without material (the loopers that end a
 // transport), the serial chain of their vacuum steps runs here, in a kernel
-// of few registers (~1.45 us per step against ~1.94 us inside the step
+// of few registers and without the step kernel's per-launch bookkeeping (a
+// lone looper in c4: ~0.95 us per step here, ~1.3 us inside the step
 // kernel), before the step kernel sees them.  A step is kept only if its track
 // stays alive in vacuum, which changes nothing but the track; the first step
 // that would end otherwise is left in the queue and taken by the step kernel
@@ -1081,9 +1083,12 @@ constexpr int kVacHelperBlock = 256;
 // function the step kernel runs for such a track.
 enum : int { kHelperLooper = 0, kHelperHelix = 1, kHelperInteg = 2 };
 
+// tracer: the lane that writes the step records (in the one-wavefront-per-
+// looper form every lane steps the same track, and lane 0 records it)
 template <class P, bool TRACE, int HM, class R = typename P::R>
 __device__ __forceinline__ void helper_steps(const BatchArgs<P>& A, const Ctx<P>& c, const WorldRun<P>& run,
-                                             Track<P>& t, int max_steps, int& calls, int& kept, RkSum& rks)
+                                             Track<P>& t, int max_steps, int& calls, int& kept, RkSum& rks,
+                                             bool tracer)
 {
     for (; calls < max_steps;) {
         Track<P> tn = t;
@@ -1098,7 +1103,7 @@ __device__ __forceinline__ void helper_steps(const BatchArgs<P>& A, const Ctx<P>
         calls += 1;
         if (o.status != kAlive) break;
         if (tn.vol != t.vol && vol_material(c_geom, tn.vol) >= 0) break;
-        if (TRACE && o.did_step) trace_step(A.S, tn, o.vol_pre, tn, o, ns);
+        if (TRACE && tracer && o.did_step) trace_step(A.S, tn, o.vol_pre, tn, o, ns);
         if constexpr (HM == kHelperInteg) {
             rks.acc += (uint32_t)o.rk.acc;
             rks.rej += (uint32_t)o.rk.rej;
@@ -1151,9 +1156,10 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
         load_track(A.in[tw], sw, tw, tu);
         const WorldRun<P> run = world_run(c, tu);
         RkSum rks{0u, 0u, 0u};
-        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, tu, max_steps, calls, kept, rks);
-        else helper_steps<P, false, HM>(A, c, run, tu, max_steps, calls, kept, rks);
-        if ((threadIdx.x & 63) == 0) {
+        const bool lane0 = (threadIdx.x & 63) == 0;
+        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, tu, max_steps, calls, kept, rks, lane0);
+        else helper_steps<P, false, HM>(A, c, run, tu, max_steps, calls, kept, rks, lane0);
+        if (lane0) {
             // (one looper per wavefront: its integration counts once, as one lane's)
             helper_rk_counts(A.S, rks);
             if (kept) {
@@ -1171,8 +1177,8 @@ __global__ void __launch_bounds__(kVacHelperBlock) k_vacuum_helper(BatchArgs<P> 
         // step records' other fields are dead.
         const WorldRun<P> run = world_run(c, t);
         RkSum rks{0u, 0u, 0u};
-        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, t, max_steps, calls, kept, rks);
-        else helper_steps<P, false, HM>(A, c, run, t, max_steps, calls, kept, rks);
+        if (A.S.trace) helper_steps<P, true, HM>(A, c, run, t, max_steps, calls, kept, rks, true);
+        else helper_steps<P, false, HM>(A, c, run, t, max_steps, calls, kept, rks, true);
         helper_rk_counts(A.S, rks);
         if (kept) {
             store_track(A.in[ty], slot, t);

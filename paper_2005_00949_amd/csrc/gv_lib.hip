@@ -871,13 +871,16 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
     hipStream_t s = stream();
     uint32_t population = counts[0] + counts[1] + counts[2];
     uint32_t peak = population;
+    bool grew = true;   // the last replay raised the population (or none has run yet)
     int64_t launches = 0;
     const int64_t bound = window_launch_bound();
     bool in_tail = false;
     for (;;) {
-        // once the population has passed its peak and fallen below the tail
-        // threshold, replay the tail graph (more launches per replay)
-        const bool tail = population < tu.tail && peak >= tu.tail;
+        // replay the tail graph (more launches per replay, the vacuum helper)
+        // once the population is below the tail threshold and past its peak:
+        // after a peak at or above the threshold, or, in a window whose
+        // population never reaches it, as soon as a replay no longer raises it
+        const bool tail = population < tu.tail && (peak >= tu.tail || !grew);
         if (tail && !in_tail) {
             // the steps taken so far, so that the tail's own steps can be told apart
             unsigned long long c3[3];
@@ -906,7 +909,9 @@ template <class P> int run_batched_window(size_t b, size_t e, uint64_t seed, con
         if (L.progress)
             std::fprintf(stderr, "[gv] replay %lld %s: %.3f ms, population %u/%u/%u\n",
                          (long long)L.stats.graph_replays, tail ? "tail" : "bulk", ms, c[0], c[1], c[2]);
+        const uint32_t before = population;
         population = c[0] + c[1] + c[2];
+        grew = population > before;
         peak = std::max(peak, population);
         if (population == 0) {
             if (in_tail) {
@@ -1495,6 +1500,7 @@ int gv_transport_staged(uint64_t seed, double* edep_out)
     L.stats.rk_lane_slots = (int64_t)cnt[kCRkSlots];
     L.stats.lane_slots = (int64_t)cnt[kCLaneSlots];
     L.stats.helper_steps = (int64_t)cnt[kCHelperSteps];
+    L.stats.rk_parked = (int64_t)cnt[kCRkParked];
     L.stats.trace_records = (int64_t)std::min<unsigned long long>(tn, (unsigned long long)L.cfg.trace_cap);
     L.stats.e_in = L.e_in;
     double ed = 0.0, es = 0.0, ek = 0.0, np_ = 0.0, na = 0.0;

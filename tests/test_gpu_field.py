@@ -189,10 +189,11 @@ def test_rk45_fixed_point_scores_bit_identical(gv):
 def test_map_tail_helper_equals_plain(gv, method):
     """c5m (the barrel in the solenoid map), 600 events, FP64 with fixed-point
     scores and a looper cap of 20,000 steps: the batched driver passes its
-    population peak and ends in the tail replays, where the helper kernel
-    steps the last loopers with the general step (the helix in the map, or
-    RK45); deposits, ledgers and step counts equal the plain driver's bit for
-    bit."""
+    population peak (with RK45: steps above the tail threshold are parked in
+    the integration queue, the others integrate inside the step) and ends in
+    the tail replays, where the helper kernel steps the last loopers with the
+    general step (the helix in the map, or RK45); deposits, ledgers and step
+    counts equal the plain driver's bit for bit."""
     geom, prim, seed = gv_inputs.workload("c5m", 600)
     fm = gv.FIELD_HELIX if method == "helix" else gv.FIELD_RK45
     out = {}
@@ -201,10 +202,14 @@ def test_map_tail_helper_equals_plain(gv, method):
                         max_steps_per_track=20_000)
         e = eng.transport(prim, seed)
         st = eng.stats()
-        out[drv] = (e, eng.ledger(), st["steps"], st["killed"], st["escaped"], st["helper_steps"], st["rk_substeps"])
+        out[drv] = (e, eng.ledger(), st["steps"], st["killed"], st["escaped"], st["helper_steps"], st["rk_substeps"],
+                    st["rk_parked"])
         eng.close()
     a, b = out[gv.DRIVER_BATCHED], out[gv.DRIVER_PLAIN]
-    print(f"\n[c5m 600 {method}] steps {sum(a[2])}, killed {a[3]}, helper steps {a[5]}, RK45 substeps {a[6]}")
+    print(f"\n[c5m 600 {method}] steps {sum(a[2])}, killed {a[3]}, helper steps {a[5]}, RK45 substeps {a[6]}, "
+          f"parked {a[7]}")
     assert a[5] > 0
+    # the integration queue took part with RK45 (and only there)
+    assert (a[7] > 0) == (method == "rk45") and b[7] == 0
     assert a[2] == b[2] and a[3] == b[3] and a[4] == b[4] and a[6] == b[6]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
