@@ -691,6 +691,7 @@ template <class P> struct BatchArgs {
     uint32_t* order[2];      // integration order per type: long moves from the front, short ones from the back
     uint32_t jcap;           // capacity per type of both
     int regime;              // which populations this step kernel launch takes (kRunAlways, ...)
+    int min_lanes;           // a wavefront with fewer tracks still stepping ends its inner steps (0: never)
 };
 
 // A launch of the integration queue's bulk graph holds two step kernels: the
@@ -829,12 +830,20 @@ __device__ __forceinline__ RkCounts rk_counts(const Ctrl* ctrl, int q, uint32_t 
     return RkCounts{(uint32_t)(h + l), (uint32_t)h};
 }
 
+// Lanes (of 64) below which a wavefront stops its inner steps in the bulk
+// replays.  A lane whose track stops early (a secondary, the end of the track)
+// would otherwise idle until the wavefront's last track has taken its inner
+// steps; the few tracks still stepping are cheaper to queue and continue in
+// the next launch.  The tail replays keep every track for its inner steps:
+// there the wavefronts are sparse by nature and each launch is short.
+constexpr int kBulkMinLanes = 32;
+
 template <class P, int TY, int BLOCK, bool STABLE, bool INTEG, bool PARK = false, class R = typename P::R>
 __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P>& c, uint32_t chunk, uint32_t base,
                                               uint32_t n_t, uint32_t epoch, int inner, ScanShared<BLOCK>& sh,
                                               DepCache& dc, unsigned* cnt_lds, uint32_t& steps_here,
                                               uint32_t& loads, uint32_t& stores, uint32_t n_chunks, RkSum& rks,
-                                              unsigned long long* lane_slots_lds, bool vac_ok)
+                                              unsigned long long* lane_slots_lds, bool vac_ok, int min_lanes)
 {
     const uint32_t slot = base + threadIdx.x;
     const bool active = slot < n_t;
@@ -852,6 +861,10 @@ __device__ __forceinline__ void process_chunk(const BatchArgs<P>& A, const Ctx<P
         DepAcc acc{0.0, 0ull};
         int acc_vol = t.vol;
         for (; iters < inner;) {
+            // a wavefront with fewer than min_lanes tracks still stepping
+            // leaves the loop: they are queued as they stand and continue
+            // in the next launch, and the wavefront takes its next chunk
+            if (iters > 0 && __popcll(__ballot(1)) < min_lanes) break;
             uint32_t ns = t.nstep;
             const bool acc_empty = (acc.e == 0.0) & (acc.x == 0ull);
             if (TY != kGamma && !INTEG && !PARK && vac_ok && __all((t.vol == 0) & acc_empty)) {
@@ -1036,15 +1049,15 @@ k_step_batched(BatchArgs<P> A)
             if (chunk < c0)
                 process_chunk<P, kGamma, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, chunk * BLOCK, n0, epoch, inner, sh, dc,
                                                                      cnt_lds, steps_g, loads, stores, n_chunks, rks,
-                                                                     &rk_lds[3], vac_ok);
+                                                                     &rk_lds[3], vac_ok, A.min_lanes);
             else if (chunk < c0 + c1)
                 process_chunk<P, kElectron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0) * BLOCK, n1, epoch, inner,
                                                                         sh, dc, cnt_lds, steps_e, loads, stores, n_chunks,
-                                                                        rks, &rk_lds[3], vac_ok);
+                                                                        rks, &rk_lds[3], vac_ok, A.min_lanes);
             else
                 process_chunk<P, kPositron, BLOCK, STABLE, INTEG, PARK>(A, c, chunk, (chunk - c0 - c1) * BLOCK, n2, epoch,
                                                                         inner, sh, dc, cnt_lds, steps_p, loads, stores,
-                                                                        n_chunks, rks, &rk_lds[3], vac_ok);
+                                                                        n_chunks, rks, &rk_lds[3], vac_ok, A.min_lanes);
         }
     }
     atomicAdd(&cnt_lds[kCSteps + kGamma], steps_g);

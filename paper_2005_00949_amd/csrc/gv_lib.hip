@@ -800,6 +800,7 @@ int capture(const Tuning& tu, int grid, int K, int inner_bulk, int inner_tail, b
         A[par].order[1] = order ? order + L.rk_jcap : nullptr;
         A[par].jcap = jobs ? L.rk_jcap : 0u;
         A[par].regime = kRunAlways;
+        A[par].min_lanes = tail ? 0 : kBulkMinLanes;
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     const bool stable = L.cfg.queue_order == GV_ORDER_STABLE;
