@@ -119,7 +119,7 @@ def run_gpu(args):
     stream = torch.cuda.current_stream()
     eng = gv.Engine(geom, driver=gv.DRIVER_BATCHED, precision=gv.PMIX, edep_on_device=1,
                     hip_stream=stream.cuda_stream, basket=args.basket, occupancy=args.occupancy,
-                    inner_steps=args.inner)
+                    inner_steps=args.inner, graph_steps=args.graph_steps)
     edep = torch.zeros((n_events, eng.n_cells), dtype=torch.float64, device="cuda:0")
     eng.stage(prim)
     log(f"[bench] workload {args.workload}: {len(prim)} primaries, {n_events} events, "
@@ -516,6 +516,8 @@ def main():
     ap.add_argument("--basket", type=int, default=0)
     ap.add_argument("--occupancy", type=int, default=0)
     ap.add_argument("--inner", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="step launches per bulk graph replay (0: the library's default)")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--testem5", type=int, default=1, help="run the single-slab leg")
     ap.add_argument("--field-map", type=int, default=1, help="run the solenoid-map (helix vs RK45) leg")
